@@ -1,0 +1,347 @@
+"""CPU oracle for NSG search — TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct C (``nsg_oracle.c``) behind ctypes.  Only the
+test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+(``paper_1707_00143_amd``) and never imports it.
+
+Each wrapper cites the passage of the paper it follows; the C source states
+every reading taken where the paper is silent or garbled.
+
+Parity status per function (see the tests named):
+  knn             pinned: NumPy FP64 brute force (test_oracle_knn)
+  search          pinned: exhaustive-L / complete-graph special cases equal
+                  exact kNN; hand-traced golden example; Theorem 1+3 greedy
+                  walk on exact MRNG; pool invariant (test_oracle_search)
+  mrng_naive      pinned: the MRNG definition checked pair by pair with
+                  open lunes in FP64 (test_oracle_build)
+  build_nsg       pinned: degree bound, reachability, NN-percentage, the
+                  pairwise rule, MRNG equivalence with uncapped candidates
+  encode/decode   pinned: NumPy float16, torch bfloat16 / float8_e4m3fn
+                  (test_oracle_precision)
+  mlp             pinned: central finite differences and torch FP64 autograd
+                  (test_oracle_mlp)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nsg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+SENT = 0xFFFFFFFF
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle (gcc -O2 -ffp-contract=off, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call([
+            "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+            "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _get():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, u32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_uint32, ctypes.c_double
+        sig = {
+            "oracle_l2sq_f32": (ctypes.c_float, [P, P, i32]),
+            "oracle_l2sq_f64": (f64, [P, P, i32]),
+            "oracle_knn": (i32, [P, i64, i32, P, i64, i32, i32, i32, P, P]),
+            "oracle_search_batch": (i32, [P, i64, i32, P, i32, u32, P, i64, i32, i32, P, P,
+                                          i32, P, P, P, P, P, P, i32, i64, P, i32]),
+            "oracle_search_one": (i32, [P, i64, i32, P, i32, u32, P, i32, i64, P, P, P,
+                                        P, i64, P, P, i64, P]),
+            "oracle_centroid": (i32, [P, i64, i32, P]),
+            "oracle_navigating_node": (i32, [P, i64, i32, P, i32, u32, i32, P]),
+            "oracle_collect_select": (i32, [P, i64, i32, P, i32, u32, i32, i32, i32, u32, P]),
+            "oracle_repair": (i32, [P, i64, i32, P, i32, u32, i32]),
+            "oracle_build_nsg": (i32, [P, i64, i32, P, i32, i32, i32, i32, u32, P, P, P, i32]),
+            "oracle_mrng_naive": (i32, [P, i64, i32, i32, P, P]),
+            "oracle_decode": (i32, [i32, P, i64, P]),
+            "oracle_encode": (i32, [i32, P, i64, P]),
+            "oracle_scales": (i32, [i32, P, i64, i32, P]),
+            "oracle_quantize": (i32, [i32, P, i64, i32, P, P, P]),
+            "oracle_rerank": (i32, [P, i32, P, i64, P, i32, i32, P, P]),
+            "oracle_mlp_nparams": (i64, [i32, i32]),
+            "oracle_mlp_loss_grad": (f64, [P, i32, i32, P, P, i64, P, P]),
+            "oracle_adam_step": (i32, [P, P, P, P, i64, i64, f64, f64, f64, f64]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(_lib, name)
+            fn.restype = res
+            fn.argtypes = args
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _u32(a):
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+    return rc
+
+
+# --------------------------------------------------------------------------
+# distances and exact kNN (Sec. 2.1 K-NNS; Sec. 4.1.2 serial scan)
+# --------------------------------------------------------------------------
+
+def l2sq_f32(a, b) -> float:
+    a, b = _f32(a), _f32(b)
+    return float(_get().oracle_l2sq_f32(_p(a), _p(b), a.shape[-1]))
+
+
+def knn(base, queries, k, prec=64, exclude_self=False):
+    """Exact kNN ordered by (squared distance, id); FP64 keys by default."""
+    base, queries = _f32(base), _f32(queries)
+    n, d = base.shape
+    nq = queries.shape[0]
+    ids = np.empty((nq, k), np.uint32)
+    dist = np.empty((nq, k), np.float64)
+    _check(_get().oracle_knn(_p(base), n, d, _p(queries), nq, k, prec,
+                             1 if exclude_self else 0, _p(ids), _p(dist)), "knn")
+    return ids, dist
+
+
+def knn_graph(base, K):
+    """Exact kNN graph: each row ordered by (FP32 squared distance, id), self
+    excluded (Algorithm 2 input, step i of Sec. 3.4, exact here)."""
+    ids, _ = knn(base, base, K, prec=32, exclude_self=True)
+    return ids
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1
+# --------------------------------------------------------------------------
+
+def search(base, graph, start, queries, k, L, k_arr=None, L_arr=None, pool_stride=0,
+           trunc_hop=-1, trunc_L=None, threads=0):
+    """Batched Algorithm 1 from `start`.  Returns (ids, dist, hops, ndist[, pool_ids,
+    pool_dist]).  With per-query k_arr / L_arr the outputs are [nq][max k]."""
+    base, graph, queries = _f32(base), _u32(graph), _f32(queries)
+    n, d = base.shape
+    R = graph.shape[1]
+    nq = queries.shape[0]
+    k_arr_c = None if k_arr is None else np.ascontiguousarray(k_arr, np.int32)
+    L_arr_c = None if L_arr is None else np.ascontiguousarray(L_arr, np.int32)
+    kst = int(k_arr_c.max()) if k_arr_c is not None and nq else k
+    ids = np.full((nq, kst), SENT, np.uint32)
+    dist = np.full((nq, kst), np.inf, np.float32)
+    hops = np.zeros(nq, np.int64)
+    nd = np.zeros(nq, np.int64)
+    pids = pd = None
+    if pool_stride:
+        pids = np.empty((nq, pool_stride), np.uint32)
+        pd = np.empty((nq, pool_stride), np.float32)
+    tl = None if trunc_L is None else np.ascontiguousarray(trunc_L, np.int32)
+    _check(_get().oracle_search_batch(
+        _p(base), n, d, _p(graph), R, int(start), _p(queries), nq, int(k), int(L),
+        _p(k_arr_c), _p(L_arr_c), kst, _p(ids), _p(dist), _p(hops), _p(nd),
+        _p(pids), _p(pd), int(pool_stride), int(trunc_hop), _p(tl), int(threads)), "search")
+    if pool_stride:
+        return ids, dist, hops, nd, pids, pd
+    return ids, dist, hops, nd
+
+
+def search_one(base, graph, start, q, L, stop_hop=-1, trace_cap=4096, vis_cap=1 << 20):
+    """One Algorithm 1 run with diagnostics: dict with pool ids/dist/checked,
+    expansion trace, visited list, hops, ndist."""
+    base, graph, q = _f32(base), _u32(graph), _f32(q)
+    n, d = base.shape
+    R = graph.shape[1]
+    pids = np.empty(L + R, np.uint32)
+    pdist = np.empty(L + R, np.float32)
+    pchk = np.empty(L + R, np.int32)
+    trace = np.empty(trace_cap, np.uint32)
+    vid = np.empty(vis_cap, np.uint32)
+    vdist = np.empty(vis_cap, np.float32)
+    stats = np.zeros(3, np.int64)
+    size = _check(_get().oracle_search_one(
+        _p(base), n, d, _p(graph), R, int(start), _p(q), int(L), int(stop_hop),
+        _p(pids), _p(pdist), _p(pchk), _p(trace), trace_cap, _p(vid), _p(vdist), vis_cap,
+        _p(stats)), "search_one")
+    h, ndist, nv = (int(x) for x in stats)
+    return dict(pool_ids=pids[:size].copy(), pool_dist=pdist[:size].copy(),
+                pool_checked=pchk[:size].astype(bool), trace=trace[:min(h, trace_cap)].copy(),
+                vis_ids=vid[:min(nv, vis_cap)].copy(), vis_dist=vdist[:min(nv, vis_cap)].copy(),
+                hops=h, ndist=ndist)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2 and the naive MRNG
+# --------------------------------------------------------------------------
+
+def centroid(base):
+    base = _f32(base)
+    c = np.empty(base.shape[1], np.float32)
+    _check(_get().oracle_centroid(_p(base), base.shape[0], base.shape[1], _p(c)), "centroid")
+    return c
+
+
+def navigating_node(base, knn_g, rand_start, Lb):
+    base, knn_g = _f32(base), _u32(knn_g)
+    nav = np.zeros(1, np.uint32)
+    _check(_get().oracle_navigating_node(_p(base), base.shape[0], base.shape[1], _p(knn_g),
+                                         knn_g.shape[1], int(rand_start), int(Lb), _p(nav)),
+           "navigating_node")
+    return int(nav[0])
+
+
+def collect_select(base, knn_g, nav, Lb, C, m, v):
+    base, knn_g = _f32(base), _u32(knn_g)
+    row = np.empty(m, np.uint32)
+    cnt = _check(_get().oracle_collect_select(_p(base), base.shape[0], base.shape[1],
+                                              _p(knn_g), knn_g.shape[1], int(nav), int(Lb),
+                                              int(C), int(m), int(v), _p(row)), "collect_select")
+    return row[:cnt].copy()
+
+
+def repair(base, graph, nav, Lb):
+    """Connectivity repair in place; returns the number of edges added."""
+    base = _f32(base)
+    assert graph.dtype == np.uint32 and graph.flags.c_contiguous
+    return _check(_get().oracle_repair(_p(base), base.shape[0], base.shape[1], _p(graph),
+                                       graph.shape[1], int(nav), int(Lb)), "repair")
+
+
+def build_nsg(base, knn_g, Lb, C, m, rand_start, threads=0):
+    """Algorithm 2.  Returns (graph [n][m] uint32 sentinel-padded, nav, repair_edges)."""
+    base, knn_g = _f32(base), _u32(knn_g)
+    n, d = base.shape
+    g = np.empty((n, m), np.uint32)
+    nav = np.zeros(1, np.uint32)
+    stats = np.zeros(4, np.int64)
+    _check(_get().oracle_build_nsg(_p(base), n, d, _p(knn_g), knn_g.shape[1], int(Lb), int(C),
+                                   int(m), int(rand_start), _p(g), _p(nav), _p(stats),
+                                   int(threads)), "build_nsg")
+    return g, int(nav[0]), int(stats[0])
+
+
+def mrng_naive(base, prec=64):
+    """Naive MRNG (Sec. 3.3).  Returns list of rows (np.uint32 arrays)."""
+    base = _f32(base)
+    n, d = base.shape
+    out = np.empty((n, n - 1), np.uint32)
+    deg = np.empty(n, np.int32)
+    _check(_get().oracle_mrng_naive(_p(base), n, d, prec, _p(out), _p(deg)), "mrng_naive")
+    return [out[i, :deg[i]].copy() for i in range(n)]
+
+
+# --------------------------------------------------------------------------
+# reduced precision (not in the paper)
+# --------------------------------------------------------------------------
+
+DTYPES = {"bf16": 1, "f16": 2, "e4m3": 3}
+
+
+def _code_dtype(dt):
+    return np.uint8 if dt == 3 else np.uint16
+
+
+def decode(dtype, codes):
+    dt = DTYPES[dtype]
+    codes = np.ascontiguousarray(codes, dtype=_code_dtype(dt))
+    out = np.empty(codes.shape, np.float32)
+    _check(_get().oracle_decode(dt, _p(codes), codes.size, _p(out)), "decode")
+    return out
+
+
+def encode(dtype, x):
+    dt = DTYPES[dtype]
+    x = _f32(x)
+    out = np.empty(x.shape, _code_dtype(dt))
+    _check(_get().oracle_encode(dt, _p(x), x.size, _p(out)), "encode")
+    return out
+
+
+def scales(dtype, base):
+    base = _f32(base)
+    s = np.empty(base.shape[1], np.float32)
+    _check(_get().oracle_scales(DTYPES[dtype], _p(base), base.shape[0], base.shape[1], _p(s)),
+           "scales")
+    return s
+
+
+def quantize(dtype, base, sc):
+    """Returns (codes [n][d], decoded rows fl32(s_j * dec(code)) [n][d])."""
+    dt = DTYPES[dtype]
+    base, sc = _f32(base), _f32(sc)
+    codes = np.empty(base.shape, _code_dtype(dt))
+    dec = np.empty(base.shape, np.float32)
+    _check(_get().oracle_quantize(dt, _p(base), base.shape[0], base.shape[1], _p(sc), _p(codes),
+                                  _p(dec)), "quantize")
+    return codes, dec
+
+
+def rerank(base, queries, pool_ids, k):
+    base, queries, pool_ids = _f32(base), _f32(queries), _u32(pool_ids)
+    nq = queries.shape[0]
+    ids = np.empty((nq, k), np.uint32)
+    dist = np.empty((nq, k), np.float32)
+    _check(_get().oracle_rerank(_p(base), base.shape[1], _p(queries), nq, _p(pool_ids),
+                                pool_ids.shape[1], int(k), _p(ids), _p(dist)), "rerank")
+    return ids, dist
+
+
+# --------------------------------------------------------------------------
+# MLP for the learned early stop (not in the paper)
+# --------------------------------------------------------------------------
+
+def mlp_nparams(n_in, h):
+    return int(_get().oracle_mlp_nparams(n_in, h))
+
+
+def mlp_loss_grad(params, X, y, n_in, h):
+    """FP64 forward + MSE + backward.  Returns (loss, grad, yhat)."""
+    params = np.ascontiguousarray(params, np.float64)
+    X = np.ascontiguousarray(X, np.float64)
+    B = X.shape[0]
+    yhat = np.empty(B, np.float64)
+    grad = None
+    yy = None
+    if y is not None:
+        yy = np.ascontiguousarray(y, np.float64)
+        grad = np.empty_like(params)
+    loss = _get().oracle_mlp_loss_grad(_p(params), n_in, h, _p(X), _p(yy), B, _p(yhat), _p(grad))
+    return float(loss), grad, yhat
+
+
+def adam_step(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place FP64 Adam step on float64 arrays."""
+    for a in (params, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _check(_get().oracle_adam_step(_p(params), _p(grad), _p(m), _p(v), params.size, int(t),
+                                   lr, b1, b2, eps), "adam")
+
+
+def recall_at_k(found_ids, gt_ids, k):
+    """precision(R') = |R' ∩ R| / K (Sec. 2.1 Eq. 1), per query; padding is a miss."""
+    found_ids = np.asarray(found_ids)[:, :k]
+    gt_ids = np.asarray(gt_ids)[:, :k]
+    out = np.empty(found_ids.shape[0])
+    for i in range(found_ids.shape[0]):
+        f = set(int(x) for x in found_ids[i] if int(x) != SENT)
+        out[i] = len(f & set(int(x) for x in gt_ids[i])) / k
+    return out
