@@ -1,0 +1,225 @@
+/*
+ * nsg.h — C ABI of libnsg.so, the MI355X (gfx950) implementation of search on
+ * a Navigating Spreading-out Graph (Fu, Xiang, Wang, Cai, PVLDB; arXiv
+ * 1707.00143).
+ *
+ * General conventions
+ *   - Pointers are HIP device pointers unless a comment says "host".
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Every call enqueues its work on `stream` and returns; results
+ *     are valid once the stream has been synchronised.  Host-side argument
+ *     checks happen before anything is enqueued: on any error nothing is
+ *     written to caller memory.
+ *   - Distances are SQUARED l2 distances in FP32 (the paper's delta is the l2
+ *     distance, Sec. 2; squaring keeps its order).  Results are ordered by
+ *     (distance, id) ascending.
+ *   - Missing results (k larger than the final candidate pool, or than the
+ *     number of points) are padded with id 0xFFFFFFFF and distance +inf.
+ *   - Graphs are [n][R] uint32, row-major: each row is its valid prefix of
+ *     neighbour ids followed by 0xFFFFFFFF sentinels (fixed out-degree
+ *     storage for contiguous access, Sec. 4.1.3).
+ *   - Return value: NSG_OK (0) or a negative nsg_status; nsg_last_error()
+ *     gives a message for the calling host thread.  No C++ exception crosses
+ *     this ABI.
+ *   - Limits: n < 2^31, 1 <= d <= 4096, 1 <= R <= 128, 1 <= L <= 512,
+ *     1 <= k <= 512.
+ */
+#ifndef NSG_H
+#define NSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nsg_index nsg_index;            /* opaque, owned by the library */
+
+typedef enum {
+    NSG_F32 = 0,   /* FP32 rows */
+    NSG_BF16 = 1,  /* bfloat16 codes with per-dimension FP32 scales */
+    NSG_F16 = 2,   /* IEEE binary16 codes with per-dimension FP32 scales */
+    NSG_E4M3 = 3   /* OCP FP8 E4M3 codes with per-dimension FP32 scales */
+} nsg_dtype;
+
+typedef enum {
+    NSG_OK = 0,
+    NSG_EINVAL = -1,       /* bad argument */
+    NSG_ENOMEM = -2,       /* device allocation failed */
+    NSG_EDEVICE = -3,      /* a HIP call failed */
+    NSG_ESTATE = -4,       /* call not valid in the current state */
+    NSG_EUNSUPPORTED = -5  /* outside the compiled limits */
+} nsg_status;
+
+/* Message for the last failing call on this host thread (host pointer, valid
+ * until the next call on the same thread). */
+const char *nsg_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Index                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Make an index resident on the current device: the point set S (Sec. 2.1)
+ * as base[n][d] FP32, its graph[n][R] and the navigating node (the fixed start
+ * of every search, Sec. 3.4 step ii and Sec. 3.5).
+ *   storage: row format the search gathers.  For reduced formats the scale of
+ *            dimension j is s_j = max_i |base[i][j]| / M (M = 448 for E4M3,
+ *            1 for BF16 / FP16; s_j = 1 for an all-zero column) unless
+ *            `scales` (device, [d]) is given; codes are round-to-nearest-even
+ *            of base/s_j with saturation.  The FP32 rows are kept as well: they
+ *            re-rank the final pool exactly.
+ * The library copies base and graph into its own padded layout; the caller
+ * may free its buffers after synchronising `stream`.  Graph entries must be
+ * < n or the sentinel, nav < n (checked on the device; a violation returns
+ * NSG_EINVAL).  *out receives the handle.
+ */
+int nsg_load_index(const float *base, int64_t n, int32_t d,
+                   const uint32_t *graph, int32_t R, uint32_t nav_node,
+                   nsg_dtype storage, const float *scales,
+                   void *stream, nsg_index **out);
+
+/* Release an index (NULL is a no-op).  Synchronises the device first. */
+void nsg_free_index(nsg_index *idx);
+
+/* Shape of a loaded index (host outputs; any may be NULL). */
+int nsg_index_info(const nsg_index *idx, int64_t *n, int32_t *d, int32_t *R,
+                   uint32_t *nav, int32_t *storage);
+
+/* ------------------------------------------------------------------------ */
+/* Search (Algorithm 1, Search-on-Graph, started at the navigating node)     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * For each of nq queries[nq][d] (FP32, row-major) run Algorithm 1 from the
+ * navigating node with candidate pool size L: repeatedly expand the nearest
+ * unchecked pool entry, compute the distance of every not yet visited
+ * neighbour, keep the L nearest by (distance, id); stop when no unchecked
+ * entry remains; return the first k.  With reduced-precision storage the
+ * walk uses the decoded rows s_j * code and the final pool is re-ranked with
+ * exact FP32 distances before the first k are emitted.
+ * Outputs out_ids[nq][k], out_dist[nq][k] (device, caller-allocated).
+ * nq = 0 is a no-op.
+ */
+int nsg_search(const nsg_index *idx, const float *queries, int64_t nq,
+               int32_t k, int32_t L, uint32_t *out_ids, float *out_dist,
+               void *stream);
+
+/* Options of nsg_search_batched (host struct; zero-initialise, then set). */
+typedef struct nsg_search_opts {
+    int32_t persistent;      /* 1: persistent grid with an atomic work counter */
+    int32_t waves_per_block; /* 0: autotuned / default */
+    int32_t hash_slots;      /* visited-filter slots per query (power of 2); 0: default */
+    int32_t blocks;          /* persistent grid size; 0: one wave per resident slot */
+    int32_t learned_stop;    /* 1: use the loaded early-stop model (needs L >= 16) */
+    int32_t rerank;          /* -1: default (on for reduced storage), 0 off, 1 on */
+    int64_t *hops;           /* device [nq] expansions per query, or NULL */
+    int64_t *ndist;          /* device [nq] distance evaluations per query, or NULL */
+    int32_t *L_used;         /* device [nq] pool size after the early stop, or NULL */
+    float *features;         /* device [nq][d + 3] early-stop features at hop 16, or NULL */
+    uint32_t *pool_ids;      /* device [nq][pool_stride] final pool ids, or NULL */
+    float *pool_dist;        /* device [nq][pool_stride] final pool distances */
+    int32_t pool_stride;
+} nsg_search_opts;
+
+/*
+ * Batched search with a per-query k[i] and L[i] (device int32 arrays, NULL =
+ * use k_scalar / L_scalar).  Outputs are [nq][out_stride] with
+ * out_stride >= max k; entries past k[i] are left untouched.  `opts` may be
+ * NULL.  Same algorithm and result definition as nsg_search: every query's
+ * output equals its own nsg_search at (k[i], L[i]).
+ */
+int nsg_search_batched(const nsg_index *idx, const float *queries, int64_t nq,
+                       const int32_t *k, const int32_t *L,
+                       int32_t k_scalar, int32_t L_scalar, int32_t out_stride,
+                       uint32_t *out_ids, float *out_dist,
+                       const nsg_search_opts *opts, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Exact K nearest neighbours (serial scan, Sec. 4.1.2 item 1; K-NNS, Sec. 2.1) */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Exact k nearest base rows of every query by squared l2 distance, ordered by
+ * (distance, id).  Candidates come from FP32 matrix-core tiles
+ * (|q|^2 + |x|^2 - 2 q.x), over-fetched, then re-ranked with exact FP32
+ * differences (sum of (q_j - x_j)^2).  exclude_self != 0: queries are the base
+ * rows themselves and query i never returns row i (kNN graph).  base[n][d],
+ * queries[nq][d] FP32; out_ids / out_dist [nq][k].  k <= 512.
+ */
+int nsg_knn_bruteforce(const float *base, int64_t n, const float *queries,
+                       int64_t nq, int32_t d, int32_t k, int32_t exclude_self,
+                       uint32_t *out_ids, float *out_dist, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Index construction on the GPU (Algorithm 2, NSGbuild(G, l, m))            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Build an NSG from base[n][d] and a kNN graph knn[n][K] (Algorithm 2):
+ * centroid; navigating node = Algorithm 1 on the kNN graph from `rand_start`
+ * with the centroid as query; for every node, search-collect on the kNN
+ * graph from the navigating node (every visited node plus the K kNN
+ * neighbours, nearest C kept) and MRNG edge selection with at most m = R
+ * edges; then DFS-tree connectivity repair from the navigating node.
+ * graph_out [n][R] (device), *nav_out (host).  *repair_edges (host, may be
+ * NULL) receives the number of edges the repair added.  Synchronous.
+ */
+int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t *knn,
+              int32_t K, int32_t Lb, int32_t C, int32_t R, uint32_t rand_start,
+              uint32_t *graph_out, uint32_t *nav_out, int64_t *repair_edges,
+              void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned early termination (an extension; not in the paper)                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Network: in = d + 3 features (query, best pool distance, ratio of the 1st
+ * to the 10th pool distance, hop count) taken after `hop` expansions,
+ * z-scored with mean[in] / inv_std[in]; two ReLU hidden layers of h units;
+ * one linear output y = predicted log2 of the pool size.  The pool is then
+ * cut to L_hat = clamp(smallest grid value >= c * 2^y, max(16, k), 512) and
+ * the search continues; a non-finite y falls back to the query's own L.
+ * blob (host) holds FP32: mean[in], inv_std[in], W1[h][in], b1[h],
+ * W2[h][h], b2[h], W3[h], b3, then `grid_n` FP32 grid values ascending.
+ */
+int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes,
+                        int32_t in, int32_t h, int32_t hop, int32_t grid_n);
+
+/* Enable (1) or disable (0) the early stop and set its calibration c > 0. */
+int nsg_set_stop_mode(nsg_index *idx, int32_t enabled, float calib_c);
+
+/*
+ * Training kernels (FP32, vector ALU).  params layout: W1[h][in], b1[h],
+ * W2[h][h], b2[h], W3[h], b3 (P = h*in + h + h*h + h + h + 1 floats).
+ * X[B][in], y[B] device FP32.  Writes yhat[B] (may be NULL), grad[P] and
+ * *loss (device scalar, may be NULL) for loss = mean (yhat - y)^2.
+ */
+int nsg_mlp_forward_backward(const float *params, int32_t in, int32_t h,
+                             const float *X, const float *y, int64_t B,
+                             float *yhat, float *grad, float *loss, void *stream);
+
+/* Adam step t (1-based) over P parameters: params, m, v updated in place. */
+int nsg_mlp_adam(float *params, const float *grad, float *m, float *v,
+                 int64_t P, int64_t t, float lr, float beta1, float beta2,
+                 float eps, void *stream);
+
+/* Forward only (inference), FP32: yhat[B]. */
+int nsg_mlp_forward(const float *params, int32_t in, int32_t h,
+                    const float *X, int64_t B, float *yhat, void *stream);
+
+/*
+ * Labels for training: for each query i and grid column j, the number of
+ * ids of found[i][j][0..k) that appear in truth[i][0..k) (found is
+ * [nq][G][k], truth [nq][k_truth] with k_truth >= k).  hits[nq][G] int32.
+ */
+int nsg_recall_hits(const uint32_t *found, int64_t nq, int32_t G, int32_t k,
+                    const uint32_t *truth, int32_t k_truth, int32_t *hits,
+                    void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSG_H */

@@ -1,0 +1,408 @@
+// C ABI of libnsg.so: index residency, argument checks, error reporting and
+// the search entry points.  Kernels live in the other sources of this library.
+#include "common.hpp"
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+#include <cmath>
+
+namespace nsg {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+// ---------------------------------------------------------------------------
+// load-time kernels: padding fill, graph validation, per-dimension scales,
+// reduced-precision encoding
+// ---------------------------------------------------------------------------
+__global__ void fill_u32_kernel(uint32_t *p, int64_t cnt, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void validate_graph_kernel(const uint32_t *g, int64_t n, int R, int R_pad,
+                                      unsigned long long *bad) {
+    unsigned long long cnt = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * R;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t v = i / R;
+        int j = (int)(i % R);
+        uint32_t u = g[v * R_pad + j];
+        if (u != NSG_SENT && (int64_t)u >= n) ++cnt;
+    }
+    if (cnt) atomicAdd(bad, cnt);
+}
+
+// column max |x_ij| as FP32 bits (non-negative floats order like their bits):
+// block b takes rows b, b + gridDim.x, ...; threads walk a row's dimensions
+__global__ void colmax_kernel(const float *x, int64_t n, int d, int ld, unsigned int *mx) {
+    for (int j0 = 0; j0 < d; j0 += blockDim.x) {
+        int j = j0 + threadIdx.x;
+        float m = 0.0f;
+        if (j < d)
+            for (int64_t i = blockIdx.x; i < n; i += gridDim.x) m = fmaxf(m, fabsf(x[i * ld + j]));
+        if (j < d) atomicMax(&mx[j], __float_as_uint(m));
+    }
+}
+
+// s_j = max_i |x_ij| / M, or 1 for an all-zero column
+__global__ void scales_finish_kernel(const unsigned int *mx, int d, float M, float *s) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < d) {
+        float m = __uint_as_float(mx[j]);
+        s[j] = m > 0.0f ? m / M : 1.0f;
+    }
+}
+
+// round-to-nearest-even encoders with saturation to the largest finite value
+__device__ inline uint32_t enc_f16(float x) {
+    if (isnan(x)) return 0x7E00u | (signbit(x) ? 0x8000u : 0u);
+    x = fminf(fmaxf(x, -65504.0f), 65504.0f);
+    return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)x);
+}
+
+__device__ inline uint32_t enc_bf16(float x) {
+    uint32_t sgn = __float_as_uint(x) & 0x80000000u;
+    if (isnan(x)) return (sgn >> 16) | 0x7FC0u;
+    const float mx = __uint_as_float(0x7F7F0000u);
+    x = fminf(fmaxf(x, -mx), mx);
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+__device__ inline uint32_t enc_e4m3(float x) {
+    uint32_t sgn = (__float_as_uint(x) >> 24) & 0x80u;
+    if (isnan(x)) return sgn | 0x7Fu;
+    float a = fminf(fabsf(x), 448.0f);
+    if (a < 0x1p-6f) {                              // subnormal binade: quantum 2^-9
+        uint32_t r = (uint32_t)rintf(a * 512.0f);     // 0..8; 8 is the smallest normal
+        return sgn | r;
+    }
+    int e = (int)((__float_as_uint(a) >> 23) & 0xFFu) - 127;   // a in [2^e, 2^(e+1))
+    float r = rintf(a * __uint_as_float((uint32_t)(127 - (e - 3)) << 23));  // a / 2^(e-3), in [8, 16]
+    uint32_t ri = (uint32_t)r;
+    if (ri == 16u) { e += 1; ri = 8u; }
+    return sgn | ((uint32_t)(e + 7) << 3) | (ri - 8u);
+}
+
+// codes[n][row_chunks * EPC] from x[n][d] (ld floats per row) and s[d]
+__global__ void encode_kernel(const float *x, int64_t n, int d, int ld, const float *s, int storage,
+                              void *codes, int row_elems) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * row_elems;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t v = i / row_elems;
+        int j = (int)(i % row_elems);
+        uint32_t c = 0;
+        if (j < d) {
+            float y = x[v * ld + j] / s[j];
+            c = storage == NSG_F16 ? enc_f16(y) : storage == NSG_BF16 ? enc_bf16(y) : enc_e4m3(y);
+        }
+        if (storage == NSG_E4M3) reinterpret_cast<uint8_t *>(codes)[i] = (uint8_t)c;
+        else reinterpret_cast<uint16_t *>(codes)[i] = (uint16_t)c;
+    }
+}
+
+static int grid_for(int64_t cnt) {
+    int64_t b = (cnt + 255) / 256;
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65536);
+}
+
+int default_hash_bits(int L) {
+    int want = L * 12, bits = 10;
+    while ((1 << bits) < want && bits < 12) ++bits;
+    return bits;
+}
+
+}  // namespace nsg
+
+using namespace nsg;
+
+extern "C" const char *nsg_last_error(void) { return g_err; }
+
+extern "C" int nsg_index_info(const nsg_index *idx, int64_t *n, int32_t *d, int32_t *R,
+                              uint32_t *nav, int32_t *storage) {
+    if (!idx) return fail(NSG_EINVAL, "index is NULL");
+    if (n) *n = idx->n;
+    if (d) *d = idx->d;
+    if (R) *R = idx->R;
+    if (nav) *nav = idx->nav;
+    if (storage) *storage = idx->storage;
+    return NSG_OK;
+}
+
+extern "C" void nsg_free_index(nsg_index *idx) {
+    if (!idx) return;
+    hipDeviceSynchronize();
+    hipFree(idx->base_f32);
+    hipFree(idx->base_lp);
+    hipFree(idx->scales);
+    hipFree(idx->graph);
+    hipFree(idx->stop.f32);
+    hipFree(idx->stop.w16);
+    hipFree(idx->stop.grid);
+    delete idx;
+}
+
+extern "C" int nsg_load_index(const float *base, int64_t n, int32_t d, const uint32_t *graph,
+                              int32_t R, uint32_t nav_node, nsg_dtype storage, const float *scales,
+                              void *stream, nsg_index **out) {
+    clear_error();
+    if (!out) return fail(NSG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!base || !graph) return fail(NSG_EINVAL, "base or graph is NULL");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(NSG_EINVAL, "n=%lld out of range [1, 2^31)", (long long)n);
+    if (d < 1 || d > kMaxD) return fail(NSG_EINVAL, "d=%d out of range [1, %d]", d, kMaxD);
+    if (R < 1 || R > kMaxR) return fail(NSG_EINVAL, "R=%d out of range [1, %d]", R, kMaxR);
+    if ((int64_t)nav_node >= n) return fail(NSG_EINVAL, "navigating node %u >= n", nav_node);
+    if (storage < NSG_F32 || storage > NSG_E4M3) return fail(NSG_EINVAL, "unknown storage %d", (int)storage);
+    hipStream_t st = (hipStream_t)stream;
+    nsg_index *ix = new nsg_index();
+    ix->n = n;
+    ix->d = d;
+    ix->R = R;
+    ix->R_pad = (R + 31) / 32 * 32;
+    ix->nav = nav_node;
+    ix->storage = storage;
+    ix->row_chunks_f32 = (d + 3) / 4;
+    const int epc = elems_per_chunk(storage);
+    ix->row_chunks = (d + epc - 1) / epc;
+    hipGetDevice(&ix->device);
+    const int ld32 = ix->row_chunks_f32 * 4;
+    auto cleanup = [&](int rc) { nsg_free_index(ix); return rc; };
+    if (hipMalloc(&ix->base_f32, sizeof(float) * n * ld32) != hipSuccess ||
+        hipMalloc(&ix->graph, sizeof(uint32_t) * n * ix->R_pad) != hipSuccess)
+        return cleanup(fail(NSG_ENOMEM, "device allocation of the index failed"));
+    hipError_t e = hipSuccess;
+    if (ld32 != d) e = hipMemsetAsync(ix->base_f32, 0, sizeof(float) * n * ld32, st);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(ix->base_f32, sizeof(float) * ld32, base, sizeof(float) * d,
+                             sizeof(float) * d, n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n * ix->R_pad)), dim3(256), 0, st,
+                           ix->graph, n * ix->R_pad, NSG_SENT);
+        e = hipMemcpy2DAsync(ix->graph, sizeof(uint32_t) * ix->R_pad, graph, sizeof(uint32_t) * R,
+                             sizeof(uint32_t) * R, n, hipMemcpyDeviceToDevice, st);
+    }
+    if (e != hipSuccess) return cleanup(fail(NSG_EDEVICE, "index copy failed: %s", hipGetErrorString(e)));
+    unsigned long long *bad = nullptr, hbad = 0;
+    if (hipMalloc(&bad, sizeof(*bad)) != hipSuccess) return cleanup(fail(NSG_ENOMEM, "alloc failed"));
+    hipMemsetAsync(bad, 0, sizeof(*bad), st);
+    hipLaunchKernelGGL(validate_graph_kernel, dim3(grid_for(n * R)), dim3(256), 0, st, ix->graph, n, R,
+                       ix->R_pad, bad);
+    e = hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(bad);
+    if (e != hipSuccess) return cleanup(fail(NSG_EDEVICE, "graph validation failed: %s", hipGetErrorString(e)));
+    if (hbad) return cleanup(fail(NSG_EINVAL, "%llu graph entries are neither < n nor the sentinel", hbad));
+    if (hipMalloc(&ix->scales, sizeof(float) * ld32) != hipSuccess)
+        return cleanup(fail(NSG_ENOMEM, "alloc failed"));
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t *>(ix->scales),
+                       (int64_t)ld32, 0x3F800000u /* 1.0f */);
+    if (storage != NSG_F32) {
+        if (scales) {
+            e = hipMemcpyAsync(ix->scales, scales, sizeof(float) * d, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return cleanup(fail(NSG_EDEVICE, "scale copy failed"));
+        } else {
+            unsigned int *mx = nullptr;
+            if (hipMalloc(&mx, sizeof(unsigned int) * d) != hipSuccess) return cleanup(fail(NSG_ENOMEM, "alloc failed"));
+            hipMemsetAsync(mx, 0, sizeof(unsigned int) * d, st);
+            hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)std::min<int64_t>(n, 1024)),
+                               dim3(d < 256 ? (d + 63) / 64 * 64 : 256), 0, st, ix->base_f32, n, d, ld32, mx);
+            hipLaunchKernelGGL(scales_finish_kernel, dim3((d + 255) / 256), dim3(256), 0, st, mx, d,
+                               storage == NSG_E4M3 ? 448.0f : 1.0f, ix->scales);
+            hipStreamSynchronize(st);
+            hipFree(mx);
+        }
+        const int row_elems = ix->row_chunks * epc;
+        const size_t esz = storage == NSG_E4M3 ? 1 : 2;
+        if (hipMalloc(&ix->base_lp, esz * n * row_elems) != hipSuccess)
+            return cleanup(fail(NSG_ENOMEM, "alloc of reduced rows failed"));
+        hipLaunchKernelGGL(encode_kernel, dim3(grid_for(n * row_elems)), dim3(256), 0, st, ix->base_f32, n, d,
+                           ld32, ix->scales, (int)storage, ix->base_lp, row_elems);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return cleanup(fail(NSG_EDEVICE, "load kernels failed: %s", hipGetErrorString(e)));
+    *out = ix;
+    return NSG_OK;
+}
+
+static int check_search_common(const nsg_index *idx, const float *queries, int64_t nq,
+                               const void *ids, const void *dist) {
+    if (!idx) return fail(NSG_EINVAL, "index is NULL");
+    if (nq < 0) return fail(NSG_EINVAL, "nq=%lld < 0", (long long)nq);
+    if (nq >= ((int64_t)1 << 31)) return fail(NSG_EINVAL, "nq too large");
+    if (nq > 0 && (!queries || !ids || !dist)) return fail(NSG_EINVAL, "NULL query or output pointer");
+    return NSG_OK;
+}
+
+static int stop_ready(const nsg_index *idx) { return idx->stop.enabled && idx->stop.f32 && idx->stop.grid; }
+
+static int stop_cap(const nsg_index *idx) {
+    return std::max(16, idx->stop.grid_n > 0 ? (int)kMaxL : 16);
+}
+
+extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
+                          uint32_t *out_ids, float *out_dist, void *stream) {
+    clear_error();
+    int rc = check_search_common(idx, queries, nq, out_ids, out_dist);
+    if (rc) return rc;
+    if (k < 1 || k > kMaxK) return fail(NSG_EINVAL, "k=%d out of range [1, %d]", k, kMaxK);
+    if (L < 1 || L > kMaxL) return fail(NSG_EINVAL, "L=%d out of range [1, %d]", L, kMaxL);
+    if (nq == 0) return NSG_OK;
+    SearchArgs a{};
+    a.idx = idx;
+    a.queries = queries;
+    a.nq = nq;
+    a.k_scalar = k;
+    a.L_scalar = L;
+    a.out_stride = k;
+    a.out_ids = out_ids;
+    a.out_dist = out_dist;
+    a.learned = stop_ready(idx) && L >= 16;
+    a.L_cap = a.learned ? std::max(L, stop_cap(idx)) : L;
+    a.hash_bits = default_hash_bits(a.L_cap);
+    a.rerank = idx->storage != NSG_F32;
+    a.start_override = NSG_SENT;
+    a.self_offset = -1;
+    a.stream = (hipStream_t)stream;
+    return launch_search(a);
+}
+
+extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, int64_t nq, const int32_t *k,
+                                  const int32_t *L, int32_t k_scalar, int32_t L_scalar, int32_t out_stride,
+                                  uint32_t *out_ids, float *out_dist, const nsg_search_opts *opts,
+                                  void *stream) {
+    clear_error();
+    int rc = check_search_common(idx, queries, nq, out_ids, out_dist);
+    if (rc) return rc;
+    if (L_scalar < 1 || L_scalar > kMaxL)
+        return fail(NSG_EINVAL, "L_scalar=%d out of range [1, %d] (it bounds every L[i])", L_scalar, kMaxL);
+    if (!k && (k_scalar < 1 || k_scalar > kMaxK)) return fail(NSG_EINVAL, "k_scalar=%d out of range", k_scalar);
+    if (out_stride < 1 || out_stride > kMaxK || (!k && out_stride < k_scalar))
+        return fail(NSG_EINVAL, "out_stride=%d invalid", out_stride);
+    nsg_search_opts o{};
+    if (opts) o = *opts;
+    o.rerank = opts ? opts->rerank : -1;
+    if (o.hash_slots && (o.hash_slots & (o.hash_slots - 1)))
+        return fail(NSG_EINVAL, "hash_slots must be a power of two");
+    if (o.hash_slots && (o.hash_slots < 64 || o.hash_slots > 16384))
+        return fail(NSG_EINVAL, "hash_slots out of range [64, 16384]");
+    if (o.waves_per_block < 0 || o.waves_per_block > 16) return fail(NSG_EINVAL, "waves_per_block out of range");
+    if (o.pool_ids && (o.pool_stride < 1 || !o.pool_dist)) return fail(NSG_EINVAL, "pool output needs stride and dist");
+    if (o.learned_stop && !stop_ready(idx)) return fail(NSG_ESTATE, "no early-stop model loaded and enabled");
+    if (o.features && !o.learned_stop) return fail(NSG_EINVAL, "features need learned_stop");
+    if (nq == 0) return NSG_OK;
+    SearchArgs a{};
+    a.idx = idx;
+    a.queries = queries;
+    a.nq = nq;
+    a.k_arr = k;
+    a.L_arr = L;
+    a.k_scalar = k_scalar;
+    a.L_scalar = L_scalar;
+    a.out_stride = out_stride;
+    a.out_ids = out_ids;
+    a.out_dist = out_dist;
+    a.learned = o.learned_stop ? 1 : 0;
+    a.L_cap = a.learned ? std::max((int)L_scalar, stop_cap(idx)) : L_scalar;
+    int hb = default_hash_bits(a.L_cap);
+    if (o.hash_slots) { hb = 0; while ((1 << hb) < o.hash_slots) ++hb; }
+    a.hash_bits = hb;
+    a.waves_per_block = o.waves_per_block;
+    a.persistent = o.persistent;
+    a.blocks = o.blocks;
+    a.rerank = o.rerank < 0 ? (idx->storage != NSG_F32) : (o.rerank != 0);
+    a.hops = o.hops;
+    a.ndist = o.ndist;
+    a.L_used = o.L_used;
+    a.features = o.features;
+    a.pool_ids = o.pool_ids;
+    a.pool_dist = o.pool_dist;
+    a.pool_stride = o.pool_stride;
+    a.start_override = NSG_SENT;
+    a.self_offset = -1;
+    a.stream = (hipStream_t)stream;
+    return launch_search(a);
+}
+
+// ---------------------------------------------------------------------------
+// learned early stop: model residency
+// ---------------------------------------------------------------------------
+extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes, int32_t in, int32_t h,
+                                   int32_t hop, int32_t grid_n) {
+    clear_error();
+    if (!idx || !blob) return fail(NSG_EINVAL, "NULL index or blob");
+    if (in != idx->d + 3) return fail(NSG_EINVAL, "model input %d must be d + 3 = %d", in, idx->d + 3);
+    if (h < 1 || h > 64) return fail(NSG_EUNSUPPORTED, "hidden width %d outside [1, 64]", h);
+    if (hop < 1) return fail(NSG_EINVAL, "hop must be >= 1");
+    if (grid_n < 1 || grid_n > 256) return fail(NSG_EINVAL, "grid_n out of range [1, 256]");
+    const size_t nf = (size_t)2 * in + (size_t)h * in + h + (size_t)h * h + h + h + 1 + grid_n;
+    if (bytes != nf * sizeof(float)) return fail(NSG_EINVAL, "blob has %zu bytes, expected %zu", bytes, nf * 4);
+    const float *b = static_cast<const float *>(blob);
+    const float *mean = b, *istd = b + in, *W1 = istd + in, *b1 = W1 + (size_t)h * in, *W2 = b1 + h;
+    const float *b2 = W2 + (size_t)h * h, *W3 = b2 + h, *b3 = W3 + h, *grid = b3 + 1;
+    for (int i = 0; i < grid_n; ++i) {
+        if (!(grid[i] >= 1.0f && grid[i] <= (float)kMaxL)) return fail(NSG_EINVAL, "grid value out of [1, 512]");
+        if (i && grid[i] <= grid[i - 1]) return fail(NSG_EINVAL, "grid must be strictly ascending");
+    }
+    std::vector<float> f32;
+    f32.insert(f32.end(), mean, mean + in);
+    f32.insert(f32.end(), istd, istd + in);
+    f32.insert(f32.end(), b1, b1 + h);
+    f32.insert(f32.end(), b2, b2 + h);
+    f32.push_back(*b3);
+    std::vector<_Float16> w;
+    w.resize((size_t)in * h + (size_t)h * h + h);
+    for (int i = 0; i < in; ++i)
+        for (int j = 0; j < h; ++j) w[(size_t)i * h + j] = (_Float16)W1[(size_t)j * in + i];
+    _Float16 *w2 = w.data() + (size_t)in * h;
+    for (int i = 0; i < h; ++i)
+        for (int j = 0; j < h; ++j) w2[(size_t)i * h + j] = (_Float16)W2[(size_t)j * h + i];
+    for (int j = 0; j < h; ++j) w2[(size_t)h * h + j] = (_Float16)W3[j];
+    StopModel sm;
+    if (hipMalloc(&sm.f32, f32.size() * 4) != hipSuccess || hipMalloc(&sm.w16, w.size() * 2) != hipSuccess ||
+        hipMalloc(&sm.grid, (size_t)grid_n * 4) != hipSuccess) {
+        hipFree(sm.f32); hipFree(sm.w16); hipFree(sm.grid);
+        return fail(NSG_ENOMEM, "model allocation failed");
+    }
+    NSG_HIP(hipMemcpy(sm.f32, f32.data(), f32.size() * 4, hipMemcpyHostToDevice));
+    NSG_HIP(hipMemcpy(sm.w16, w.data(), w.size() * 2, hipMemcpyHostToDevice));
+    NSG_HIP(hipMemcpy(sm.grid, grid, (size_t)grid_n * 4, hipMemcpyHostToDevice));
+    sm.in = in;
+    sm.h = h;
+    sm.hop = hop;
+    sm.grid_n = grid_n;
+    sm.enabled = idx->stop.enabled;
+    sm.calib_c = idx->stop.calib_c;
+    hipDeviceSynchronize();
+    hipFree(idx->stop.f32);
+    hipFree(idx->stop.w16);
+    hipFree(idx->stop.grid);
+    idx->stop = sm;
+    return NSG_OK;
+}
+
+extern "C" int nsg_set_stop_mode(nsg_index *idx, int32_t enabled, float calib_c) {
+    clear_error();
+    if (!idx) return fail(NSG_EINVAL, "index is NULL");
+    if (enabled && !idx->stop.f32) return fail(NSG_ESTATE, "no early-stop model loaded");
+    if (!(calib_c > 0.0f) || !std::isfinite(calib_c)) return fail(NSG_EINVAL, "calibration must be finite and > 0");
+    idx->stop.enabled = enabled ? 1 : 0;
+    idx->stop.calib_c = calib_c;
+    return NSG_OK;
+}

@@ -1,0 +1,115 @@
+// Internal declarations shared by the sources of libnsg.so (GPU library only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/nsg.h"
+
+#define NSG_SENT 0xFFFFFFFFu
+
+namespace nsg {
+
+constexpr int kMaxL = 512;
+constexpr int kMaxR = 128;
+constexpr int kMaxK = 512;
+constexpr int kMaxD = 1024;
+constexpr int kWave = 64;
+
+// ---- error reporting (thread-local message) -------------------------------
+int fail(int code, const char *fmt, ...);
+void clear_error();
+
+#define NSG_HIP(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return ::nsg::fail(NSG_EDEVICE, "%s failed: %s (%s:%d)", #call,     \
+                               hipGetErrorString(e_), __FILE__, __LINE__);     \
+    } while (0)
+
+// ---- the index object ------------------------------------------------------
+struct StopModel {
+    float *f32 = nullptr;      // device: mean[in], inv_std[in], b1[h], b2[h], b3
+    void *w16 = nullptr;       // device FP16: W1T[in][h], W2T[h][h], W3[h]
+    float *grid = nullptr;     // device: grid values (ascending)
+    int in = 0, h = 0, hop = 0, grid_n = 0;
+    int enabled = 0;
+    float calib_c = 1.0f;
+};
+
+}  // namespace nsg
+
+struct nsg_index {
+    int64_t n = 0;
+    int32_t d = 0;
+    int32_t R = 0, R_pad = 0;
+    uint32_t nav = 0;
+    int32_t storage = NSG_F32;
+    int32_t row_chunks = 0;      // 16-byte chunks per row of the search format
+    int32_t row_chunks_f32 = 0;  // 16-byte chunks per FP32 row
+    float *base_f32 = nullptr;   // [n][row_chunks_f32 * 4]
+    void *base_lp = nullptr;     // [n][row_chunks * 16 bytes] for reduced formats
+    float *scales = nullptr;     // [row_chunks_f32 * 4]
+    uint32_t *graph = nullptr;   // [n][R_pad]
+    int device = 0;
+    nsg::StopModel stop;
+};
+
+namespace nsg {
+
+// elements per 16-byte chunk of a storage format
+inline int elems_per_chunk(int storage) {
+    return storage == NSG_F32 ? 4 : (storage == NSG_E4M3 ? 16 : 8);
+}
+
+struct SearchArgs {
+    const nsg_index *idx;
+    const float *queries;
+    int64_t nq;
+    const int32_t *k_arr;
+    const int32_t *L_arr;
+    int32_t k_scalar, L_scalar, out_stride;
+    uint32_t *out_ids;
+    float *out_dist;
+    int32_t L_cap;          // pool capacity in LDS
+    int32_t hash_bits;
+    int32_t waves_per_block;
+    int32_t persistent;
+    int32_t blocks;
+    int32_t rerank;
+    int32_t learned;
+    int64_t *hops;
+    int64_t *ndist;
+    int32_t *L_used;
+    float *features;
+    uint32_t *pool_ids;
+    float *pool_dist;
+    int32_t pool_stride;
+    // search a caller-supplied graph instead of idx->graph (index build)
+    const uint32_t *graph_override;
+    int32_t R_override, Rpad_override;
+    uint32_t start_override;  // NSG_SENT: use idx->nav
+    // per-query start node (index build: NULL)
+    const uint32_t *start_arr;
+    // record visited nodes (index build): [nq][vis_cap] ids and distances, counts
+    uint32_t *vis_ids;
+    float *vis_dist;
+    int32_t *vis_cnt;
+    int32_t vis_cap;
+    int64_t self_offset;      // >= 0: query i is base row self_offset + i (index build), else -1
+    hipStream_t stream;
+};
+
+int launch_search(const SearchArgs &a);
+
+// FP32 mean of the rows of x[n][d] (FP64 sums; acc[d] must be zeroed)
+int launch_mean(const float *x, int64_t n, int d, float *mu, double *acc, hipStream_t st);
+
+// visited-filter size (log2 slots) used for a pool of L entries
+int default_hash_bits(int L);
+
+// choose lanes-per-row and chunks-per-lane for a row of `chunks` chunks
+void pick_layout(int chunks, int max_cpl, int *lpr, int *cpl);
+
+}  // namespace nsg

@@ -1,0 +1,500 @@
+// Batched Search-on-Graph (Algorithm 1) on gfx950: one 64-lane wavefront per
+// query.  Per wave, LDS holds the candidate pool (sorted (distance, id) keys,
+// checked flag in bit 31 of the id), a visited filter (open addressing,
+// insert-if-absent; it may forget a node but never reports an unseen node as
+// seen, so results are unchanged: a forgotten node is recomputed and either
+// found in the pool by key or rejected by the L-th key), and the candidate list
+// of the current expansion.  Neighbour rows are gathered with 16-byte loads,
+// LPR lanes per row; distances are FP32 (sum of (q_j - x_j)^2) reduced across
+// the row's lanes.  New candidates are sorted with a wave bitonic network and
+// merged into the pool by merge-path positions.
+#include "wave.hpp"
+
+#include <algorithm>
+
+namespace nsg {
+
+struct KParams {
+    const uint4 *rows;           // search-format rows, stride row_chunks
+    const float *scales;         // [row_chunks * EPC] (reduced formats)
+    const float *rows_f32;       // FP32 rows for re-ranking, stride row_chunks_f32 * 4
+    const uint32_t *graph;
+    int R, R_pad;
+    int d, row_chunks, row_chunks_f32;
+    uint32_t start;
+    const float *queries;
+    int64_t nq;
+    const int32_t *k_arr, *L_arr;
+    int k_scalar, L_scalar, out_stride;
+    uint32_t *out_ids;
+    float *out_dist;
+    int L_cap, L_alloc, hash_bits, lds_per_wave, feat_cap;
+    int rerank;
+    unsigned int *counter;
+    int64_t *hops, *ndist;
+    int32_t *L_used;
+    float *features;
+    uint32_t *pool_ids;
+    float *pool_dist;
+    int pool_stride;
+    uint32_t *vis_ids;
+    float *vis_dist;
+    int32_t *vis_cnt;
+    int vis_cap;
+    int64_t self_offset;         // >= 0: query i is base row self_offset + i; its own row is visited at the end
+    // learned early stop
+    const float *stop_f32;       // mean[in], inv_std[in], b1[h], b2[h], b3
+    const _Float16 *stop_w;      // W1T[in][h], W2T[h][h], W3[h]
+    const float *grid;
+    int s_in, s_h, s_hop, grid_n;
+    float calib_c;
+    int learned;
+};
+
+// exact FP32 squared distances over the FP32 rows (re-rank), 16 lanes per row
+__device__ inline void rerank_dist(const KParams &p, const float *q, uint64_t *pool,
+                                   int size, int lane) {
+    const int g = lane >> 4, li = lane & 15;
+    const int rc = p.row_chunks_f32;
+    for (int r0 = 0; r0 < size; r0 += 4) {
+        int r = r0 + g;
+        bool ok = r < size;
+        uint32_t id = ok ? key_id(pool[r]) : 0u;
+        const float4 *row = reinterpret_cast<const float4 *>(p.rows_f32) + (int64_t)id * rc;
+        float acc = 0.0f;
+        for (int ch = li; ch < rc; ch += 16) {
+            if (!ok) break;
+            float4 x = row[ch];
+            float xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int j = ch * 4 + e;
+                float qj = j < p.d ? q[j] : 0.0f;
+                float t = qj - xs[e];
+                acc = fmaf(t, t, acc);
+            }
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        wave_sync();
+        if (li == 0 && ok) pool[r] = mk_key(acc, id);
+        wave_sync();
+    }
+}
+
+// ascending bitonic sort of pool[0..n) in LDS (n <= 1024), padding with KEY_NONE
+__device__ inline void lds_sort(uint64_t *a, int n, int cap, int lane) {
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = n + lane; i < np && i < cap; i += 64) a[i] = KEY_NONE;
+    wave_sync();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < np; i += 64) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    uint64_t x = a[i] & KEY_MASK, y = a[ixj] & KEY_MASK;
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) { uint64_t t = a[i]; a[i] = a[ixj]; a[ixj] = t; }
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+// learned early stop: features -> MLP (FP16 weights, FP32 accumulate) -> L_hat
+__device__ inline int stop_predict(const KParams &p, const float *q, const uint64_t *pool,
+                                   int size, int64_t hops, int Lq, int kq, float *xbuf,
+                                   int lane, int64_t qi) {
+    const int in = p.s_in, h = p.s_h;
+    const float d0 = key_dist(pool[0]);
+    const float d9 = key_dist(pool[size > 10 ? 9 : size - 1]);
+    for (int i = lane; i < in; i += 64) {
+        float f;
+        if (i < p.d) f = q[i];
+        else if (i == p.d) f = d0;
+        else if (i == p.d + 1) f = d9 > 0.0f ? d0 / d9 : 1.0f;
+        else f = (float)hops;
+        if (p.features) p.features[qi * (int64_t)in + i] = f;
+        xbuf[i] = (f - p.stop_f32[i]) * p.stop_f32[in + i];
+    }
+    wave_sync();
+    const float *b1 = p.stop_f32 + 2 * in;
+    const float *b2 = b1 + h;
+    const float b3 = b2[h];
+    const _Float16 *W1T = p.stop_w;
+    const _Float16 *W2T = W1T + (int64_t)in * h;
+    const _Float16 *W3 = W2T + (int64_t)h * h;
+    float a1 = 0.0f;
+    if (lane < h) {
+        float s = b1[lane];
+        for (int i = 0; i < in; ++i) s = fmaf((float)W1T[(int64_t)i * h + lane], xbuf[i], s);
+        a1 = s > 0.0f ? s : 0.0f;
+    }
+    float a2 = 0.0f;
+    {
+        float s = lane < h ? b2[lane] : 0.0f;
+        for (int j = 0; j < h; ++j) {
+            float aj = __shfl(a1, j);
+            if (lane < h) s = fmaf((float)W2T[j * h + lane], aj, s);
+        }
+        a2 = (lane < h && s > 0.0f) ? s : 0.0f;
+    }
+    float o = lane < h ? (float)W3[lane] * a2 : 0.0f;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) o += __shfl_xor(o, off);
+    o += b3;
+    wave_sync();
+    if (!isfinite(o)) return Lq;
+    float t = p.calib_c * exp2f(o);
+    int pick = p.grid_n > 0 ? (int)p.grid[p.grid_n - 1] : kMaxL;
+    for (int b = 0; b < p.grid_n; b += 64) {
+        int i = b + lane;
+        bool ge = i < p.grid_n && p.grid[i] >= t;
+        uint64_t bm = __ballot(ge);
+        if (bm) { pick = (int)p.grid[b + __ffsll((long long)bm) - 1]; break; }
+    }
+    int lo = kq > 16 ? kq : 16;
+    if (pick < lo) pick = lo;
+    if (pick > p.L_cap) pick = p.L_cap;
+    return pick;
+}
+
+template <int DT, int LPR, int CPL>
+__global__ void __launch_bounds__(256) search_kernel(KParams p) {
+    constexpr int EPC = Fmt<DT>::EPC;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    unsigned char *wbase = smem + (size_t)wave * p.lds_per_wave;
+    uint64_t *pool = reinterpret_cast<uint64_t *>(wbase);
+    uint32_t *hash = reinterpret_cast<uint32_t *>(pool + p.L_alloc);
+    uint32_t *cid = hash + (1 << p.hash_bits);
+    float *cdist = reinterpret_cast<float *>(cid + kMaxR);
+    uint32_t *spos = reinterpret_cast<uint32_t *>(cdist + kMaxR);
+    float *xbuf = reinterpret_cast<float *>(spos + 64);
+    const int H = 1 << p.hash_bits;
+
+    int64_t qi;
+    if (p.counter) {
+        unsigned int t = 0;
+        if (lane == 0) t = atomicAdd(p.counter, 1u);
+        qi = __shfl((int)t, 0);
+    } else {
+        qi = (int64_t)blockIdx.x * wpb + wave;
+    }
+    while (qi < p.nq) {
+        const float *q = p.queries + qi * (int64_t)p.d;
+        int kq = p.k_arr ? p.k_arr[qi] : p.k_scalar;
+        kq = kq < 0 ? 0 : (kq > p.out_stride ? p.out_stride : kq);
+        int Lq = p.L_arr ? p.L_arr[qi] : p.L_scalar;
+        Lq = Lq < 1 ? 1 : (Lq > p.L_cap ? p.L_cap : Lq);
+        const bool learned = p.learned && Lq >= 16;
+        int Lcur = learned ? p.L_cap : Lq;
+
+        // query chunks in registers, aligned with the row chunks this lane reads
+        float qv[CPL][EPC], sc[CPL][EPC];
+        {
+            const int li = lane % LPR;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                int ch = li + c * LPR;
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) {
+                    int j = ch * EPC + e;
+                    bool ok = ch < p.row_chunks && j < p.d;
+                    qv[c][e] = ok ? q[j] : 0.0f;
+                    sc[c][e] = (DT != NSG_F32 && ok) ? p.scales[j] : 0.0f;
+                }
+            }
+        }
+        for (int i = lane; i < H; i += 64) hash[i] = NSG_SENT;
+        wave_sync();
+
+        const uint32_t start = p.start;
+        int64_t hops = 0, nd = 0;
+        int vcount = 0;
+        int size = 0;
+        const bool rec = p.vis_ids != nullptr;
+
+        // pool <- {start}
+        if (lane == 0) { cid[0] = start; hash_insert(hash, p.hash_bits, start); }
+        wave_sync();
+        gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, qv, sc, cid, cdist, 1, lane);
+        wave_sync();
+        nd = 1;
+        if (rec && lane == 0 && vcount < p.vis_cap) {
+            p.vis_ids[qi * (int64_t)p.vis_cap + vcount] = start;
+            p.vis_dist[qi * (int64_t)p.vis_cap + vcount] = cdist[0];
+        }
+        vcount = 1;
+        if (lane == 0) pool[0] = mk_key(cdist[0], start);
+        size = 1;
+        wave_sync();
+        int cursor = 0;
+        bool stopped = !learned;   // true once the early-stop decision was taken
+
+        for (;;) {
+            int i = find_unchecked(pool, cursor, size, lane);
+            if (i < 0) break;
+            uint64_t pe = pool[i];
+            wave_sync();
+            if (lane == 0) pool[i] = pe | CHECKED_BIT;
+            const uint32_t v = key_id(pe);
+            ++hops;
+            // neighbour ids (one coalesced row), visited filter, compaction
+            const uint32_t *grow = p.graph + (int64_t)v * p.R_pad;
+            int cnt = 0;
+            for (int b = 0; b < p.R; b += 64) {
+                int j = b + lane;
+                uint32_t u = j < p.R ? grow[j] : NSG_SENT;
+                bool nw = u != NSG_SENT && hash_insert(hash, p.hash_bits, u);
+                uint64_t bm = __ballot(nw);
+                int rank = __popcll(bm & ((1ull << lane) - 1ull));
+                if (nw) cid[cnt + rank] = u;
+                cnt += __popcll(bm);
+            }
+            wave_sync();
+            if (cnt > 0) {
+                gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, qv, sc, cid, cdist, cnt, lane);
+                wave_sync();
+                nd += cnt;
+                if (rec) {
+                    for (int r = lane; r < cnt; r += 64)
+                        if (vcount + r < p.vis_cap) {
+                            p.vis_ids[qi * (int64_t)p.vis_cap + vcount + r] = cid[r];
+                            p.vis_dist[qi * (int64_t)p.vis_cap + vcount + r] = cdist[r];
+                        }
+                }
+                vcount += cnt;
+                // keep candidates below the current L-th key, merge in rounds of 64
+                int first = size;
+                for (int b = 0; b < cnt; b += 64) {
+                    const uint64_t worst = size >= Lcur ? (pool[Lcur - 1] & KEY_MASK) : KEY_NONE;
+                    int r = b + lane;
+                    uint64_t key = KEY_NONE;
+                    if (r < cnt) {
+                        uint64_t kk = mk_key(cdist[r], cid[r]);
+                        if (kk < worst) key = kk;
+                    }
+                    int fi;
+                    size = merge_pool(pool, size, Lcur, key, spos, lane, &fi);
+                    first = fi < first ? fi : first;
+                }
+                cursor = (i + 1) < first ? (i + 1) : first;
+            } else {
+                cursor = i + 1;
+            }
+            if (!stopped && hops >= p.s_hop) {
+                stopped = true;
+                int Lh = stop_predict(p, q, pool, size, hops, Lq, kq, xbuf, lane, qi);
+                Lcur = Lh;
+                if (size > Lcur) size = Lcur;
+                if (cursor > size) cursor = size;
+            }
+        }
+        if (learned && !stopped) {
+            // ended before the decision point: the result equals the plain one
+            if (p.features) for (int t = lane; t < p.s_in; t += 64) p.features[qi * (int64_t)p.s_in + t] = NAN;
+            Lcur = Lq;
+            if (size > Lcur) size = Lcur;
+        }
+        if (p.self_offset >= 0) {
+            // index build: also visit the query node's own row (its kNN list)
+            const uint32_t self = (uint32_t)(p.self_offset + qi);
+            const uint32_t *grow = p.graph + (int64_t)self * p.R_pad;
+            int cnt = 0;
+            for (int b = 0; b < p.R; b += 64) {
+                int j = b + lane;
+                uint32_t u = j < p.R ? grow[j] : NSG_SENT;
+                bool nw = u != NSG_SENT && hash_insert(hash, p.hash_bits, u);
+                uint64_t bm = __ballot(nw);
+                int rank = __popcll(bm & ((1ull << lane) - 1ull));
+                if (nw) cid[cnt + rank] = u;
+                cnt += __popcll(bm);
+            }
+            wave_sync();
+            if (cnt > 0) {
+                gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, qv, sc, cid, cdist, cnt, lane);
+                wave_sync();
+                if (rec)
+                    for (int r = lane; r < cnt; r += 64)
+                        if (vcount + r < p.vis_cap) {
+                            p.vis_ids[qi * (int64_t)p.vis_cap + vcount + r] = cid[r];
+                            p.vis_dist[qi * (int64_t)p.vis_cap + vcount + r] = cdist[r];
+                        }
+                vcount += cnt;
+            }
+        }
+        if (p.pool_ids) {
+            for (int j = lane; j < p.pool_stride; j += 64) {
+                bool ok = j < size;
+                p.pool_ids[qi * (int64_t)p.pool_stride + j] = ok ? key_id(pool[j]) : NSG_SENT;
+                p.pool_dist[qi * (int64_t)p.pool_stride + j] = ok ? key_dist(pool[j]) : INFINITY;
+            }
+        }
+        if (p.rerank) {
+            wave_sync();
+            rerank_dist(p, q, pool, size, lane);
+            lds_sort(pool, size, p.L_alloc, lane);
+        }
+        for (int j = lane; j < kq; j += 64) {
+            bool ok = j < size;
+            p.out_ids[qi * (int64_t)p.out_stride + j] = ok ? key_id(pool[j]) : NSG_SENT;
+            p.out_dist[qi * (int64_t)p.out_stride + j] = ok ? key_dist(pool[j]) : INFINITY;
+        }
+        if (lane == 0) {
+            if (p.hops) p.hops[qi] = hops;
+            if (p.ndist) p.ndist[qi] = nd;
+            if (p.L_used) p.L_used[qi] = Lcur;
+            if (p.vis_cnt) p.vis_cnt[qi] = vcount;
+        }
+        wave_sync();
+        if (!p.counter) break;
+        unsigned int t = 0;
+        if (lane == 0) t = atomicAdd(p.counter, 1u);
+        qi = __shfl((int)t, 0);
+    }
+}
+
+// ------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------
+void pick_layout(int chunks, int max_cpl, int *lpr, int *cpl) {
+    // the fewest lanes per row whose chunks fit in at most max_cpl per lane
+    int l = 8;
+    while (l < 64 && l * max_cpl < chunks) l <<= 1;
+    int c = (chunks + l - 1) / l;
+    if (c == 3) c = 4;
+    *lpr = l;
+    *cpl = c;
+}
+
+__global__ void reset_counter_kernel(unsigned int *c) { if (threadIdx.x == 0) c[0] = 0u; }
+
+typedef void (*kfn_t)(KParams);
+
+template <int DT>
+static kfn_t pick_kernel(int lpr, int cpl) {
+#define NSG_K(L_, C_) if (lpr == L_ && cpl == C_) return search_kernel<DT, L_, C_>;
+    NSG_K(8, 1) NSG_K(8, 2) NSG_K(8, 4)
+    NSG_K(16, 1) NSG_K(16, 2) NSG_K(16, 4)
+    NSG_K(32, 1) NSG_K(32, 2) NSG_K(32, 4)
+    NSG_K(64, 1) NSG_K(64, 2) NSG_K(64, 4)
+#undef NSG_K
+    return nullptr;
+}
+
+int launch_search(const SearchArgs &a) {
+    const nsg_index *ix = a.idx;
+    if (a.nq == 0) return NSG_OK;
+    KParams p{};
+    const bool lp = ix->storage != NSG_F32;
+    p.rows = reinterpret_cast<const uint4 *>(lp ? ix->base_lp : (const void *)ix->base_f32);
+    p.scales = ix->scales;
+    p.rows_f32 = ix->base_f32;
+    p.graph = a.graph_override ? a.graph_override : ix->graph;
+    p.R = a.graph_override ? a.R_override : ix->R;
+    p.R_pad = a.graph_override ? a.Rpad_override : ix->R_pad;
+    p.d = ix->d;
+    p.row_chunks = ix->row_chunks;
+    p.row_chunks_f32 = ix->row_chunks_f32;
+    p.start = a.start_override != NSG_SENT ? a.start_override : ix->nav;
+    p.queries = a.queries;
+    p.nq = a.nq;
+    p.k_arr = a.k_arr;
+    p.L_arr = a.L_arr;
+    p.k_scalar = a.k_scalar;
+    p.L_scalar = a.L_scalar;
+    p.out_stride = a.out_stride;
+    p.out_ids = a.out_ids;
+    p.out_dist = a.out_dist;
+    p.L_cap = a.L_cap;
+    p.hash_bits = a.hash_bits;
+    p.rerank = a.rerank;
+    p.hops = a.hops;
+    p.ndist = a.ndist;
+    p.L_used = a.L_used;
+    p.features = a.features;
+    p.pool_ids = a.pool_ids;
+    p.pool_dist = a.pool_dist;
+    p.pool_stride = a.pool_stride;
+    p.vis_ids = a.vis_ids;
+    p.vis_dist = a.vis_dist;
+    p.vis_cnt = a.vis_cnt;
+    p.vis_cap = a.vis_cap;
+    p.self_offset = a.self_offset;
+    p.learned = 0;
+    p.feat_cap = 0;
+    if (a.learned) {
+        const StopModel &sm = ix->stop;
+        p.learned = 1;
+        p.stop_f32 = sm.f32;
+        p.stop_w = reinterpret_cast<const _Float16 *>(sm.w16);
+        p.grid = sm.grid;
+        p.s_in = sm.in;
+        p.s_h = sm.h;
+        p.s_hop = sm.hop;
+        p.grid_n = sm.grid_n;
+        p.calib_c = sm.calib_c;
+        p.feat_cap = (sm.in + 3) & ~3;
+    }
+    int L_alloc = 1;
+    while (L_alloc < a.L_cap) L_alloc <<= 1;
+    p.L_alloc = L_alloc;
+    size_t per_wave = (size_t)L_alloc * 8 + ((size_t)4 << a.hash_bits) + kMaxR * 8 + 64 * 4 +
+                      (size_t)p.feat_cap * 4;
+    per_wave = (per_wave + 15) & ~(size_t)15;
+    p.lds_per_wave = (int)per_wave;
+    int wpb = a.waves_per_block;
+    if (wpb <= 0) {
+        wpb = 4;
+        while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
+    }
+    if (per_wave * wpb > 160 * 1024)
+        return fail(NSG_EUNSUPPORTED, "search needs %zu bytes of LDS per block", per_wave * wpb);
+    int lpr, cpl;
+    pick_layout(ix->row_chunks, ix->storage == NSG_E4M3 ? 2 : 4, &lpr, &cpl);
+    kfn_t fn = nullptr;
+    switch (ix->storage) {
+    case NSG_F32: fn = pick_kernel<NSG_F32>(lpr, cpl); break;
+    case NSG_BF16: fn = pick_kernel<NSG_BF16>(lpr, cpl); break;
+    case NSG_F16: fn = pick_kernel<NSG_F16>(lpr, cpl); break;
+    case NSG_E4M3: fn = pick_kernel<NSG_E4M3>(lpr, cpl); break;
+    }
+    if (!fn) return fail(NSG_EUNSUPPORTED, "no search kernel for %d chunks per row", ix->row_chunks);
+    size_t lds = per_wave * wpb;
+    if (lds > 64 * 1024) NSG_HIP(hipFuncSetAttribute((const void *)fn,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    unsigned int *counter = nullptr;
+    int64_t blocks;
+    if (a.persistent) {
+        NSG_HIP(hipMallocAsync((void **)&counter, sizeof(unsigned int) * 64, a.stream));
+        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, a.stream, counter);
+        int per_cu = 0;
+        NSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 64 * wpb, lds));
+        int dev = 0, cus = 0;
+        NSG_HIP(hipGetDevice(&dev));
+        NSG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        blocks = a.blocks > 0 ? a.blocks : (int64_t)std::max(1, per_cu) * cus;
+        int64_t need = (a.nq + wpb - 1) / wpb;
+        if (blocks > need) blocks = need;
+        p.counter = counter;
+        // every wave takes its first query from the counter too
+    } else {
+        blocks = (a.nq + wpb - 1) / wpb;
+        p.counter = nullptr;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, p);
+    hipError_t e = hipGetLastError();
+    if (counter) {
+        hipError_t e2 = hipFreeAsync(counter, a.stream);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return fail(NSG_EDEVICE, "search launch failed: %s", hipGetErrorString(e));
+    return NSG_OK;
+}
+
+}  // namespace nsg

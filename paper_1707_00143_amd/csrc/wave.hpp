@@ -1,0 +1,246 @@
+// Wavefront primitives shared by the search and index-build kernels of
+// libnsg.so: storage-format decoding, LDS pool merge, visited filter and the
+// row-gather distance routine.  One 64-lane wave works on one query.
+#pragma once
+#include "common.hpp"
+
+namespace nsg {
+
+#define KEY_MASK 0xFFFFFFFF7FFFFFFFull
+#define CHECKED_BIT 0x80000000ull
+#define KEY_NONE 0xFFFFFFFFFFFFFFFFull
+
+// ------------------------------------------------------------------------
+// storage formats: decode one 16-byte chunk into EPC floats
+// ------------------------------------------------------------------------
+template <int DT> struct Fmt;
+template <> struct Fmt<NSG_F32> {
+    static constexpr int EPC = 4;
+    __device__ static inline void dec(const uint4 r, float *o) {
+        o[0] = __uint_as_float(r.x); o[1] = __uint_as_float(r.y);
+        o[2] = __uint_as_float(r.z); o[3] = __uint_as_float(r.w);
+    }
+};
+template <> struct Fmt<NSG_BF16> {
+    static constexpr int EPC = 8;
+    __device__ static inline void dec(const uint4 r, float *o) {
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = __uint_as_float(w[i] << 16);
+            o[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
+        }
+    }
+};
+template <> struct Fmt<NSG_F16> {
+    static constexpr int EPC = 8;
+    __device__ static inline void dec(const uint4 r, float *o) {
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = (float)__builtin_bit_cast(_Float16, (unsigned short)(w[i] & 0xFFFFu));
+            o[2 * i + 1] = (float)__builtin_bit_cast(_Float16, (unsigned short)(w[i] >> 16));
+        }
+    }
+};
+// OCP FP8 E4M3 (bias 7, no infinities, S.1111.111 is NaN), decoded from its fields
+__device__ inline float e4m3_to_f32(uint32_t b) {
+    uint32_t s = (b & 0x80u) << 24;
+    uint32_t e = (b >> 3) & 0xFu;
+    uint32_t m = b & 7u;
+    float nrm = __uint_as_float(((e + 120u) << 23) | (m << 20));
+    float sub = (float)m * 0x1p-9f;
+    float v = e ? nrm : sub;
+    v = (e == 15u && m == 7u) ? __uint_as_float(0x7FC00000u) : v;
+    return __uint_as_float(__float_as_uint(v) | s);
+}
+template <> struct Fmt<NSG_E4M3> {
+    static constexpr int EPC = 16;
+    __device__ static inline void dec(const uint4 r, float *o) {
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[4 * i + j] = e4m3_to_f32((w[i] >> (8 * j)) & 0xFFu);
+    }
+};
+
+// ------------------------------------------------------------------------
+// wave primitives
+// ------------------------------------------------------------------------
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
+    uint32_t lo = __shfl_xor((unsigned int)(v & 0xFFFFFFFFu), m);
+    uint32_t hi = __shfl_xor((unsigned int)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t mk_key(float d, uint32_t id) {
+    return ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)id;
+}
+__device__ inline float key_dist(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ inline uint32_t key_id(uint64_t k) { return (uint32_t)(k & 0x7FFFFFFFu); }
+
+// ascending bitonic sort of one key per lane across the 64 lanes
+__device__ inline uint64_t wave_sort64(uint64_t key, int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            uint64_t o = shfl_xor64(key, j);
+            bool up = (lane & k) == 0;
+            bool lower = (lane & j) == 0;
+            uint64_t mn = key < o ? key : o;
+            uint64_t mx = key < o ? o : key;
+            key = (lower == up) ? mn : mx;
+        }
+    }
+    return key;
+}
+
+// insert-if-absent; true when u was not in the table (or could not be placed)
+__device__ inline bool hash_insert(uint32_t *tab, int bits, uint32_t u) {
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t h = (u * 2654435761u) >> (32 - bits);
+#pragma unroll 1
+    for (int t = 0; t < 16; ++t) {
+        uint32_t old = atomicCAS(&tab[h], NSG_SENT, u);
+        if (old == NSG_SENT) return true;
+        if (old == u) return false;
+        h = (h + 1u) & mask;
+    }
+    return true;
+}
+
+// index of the first unchecked pool entry at or after `from`, -1 if none
+__device__ inline int find_unchecked(const uint64_t *pool, int from, int size, int lane) {
+    for (int b = from; b < size; b += 64) {
+        int i = b + lane;
+        bool unc = i < size && !(pool[i] & CHECKED_BIT);
+        uint64_t bm = __ballot(unc);
+        if (bm) return b + __ffsll((long long)bm) - 1;
+    }
+    return -1;
+}
+
+__device__ inline int lower_bound_pool(const uint64_t *pool, int size, uint64_t key) {
+    int lo = 0, hi = size;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if ((pool[mid] & KEY_MASK) < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Merge up to 64 candidate keys (one per lane, KEY_NONE = empty) into the
+// sorted pool of `size` entries, keeping the first Lcur.  Candidates equal to
+// a pool key (a node the visited filter forgot) are dropped, keeping the pool
+// entry and its checked flag.  Returns the new size; *first_ins receives the
+// smallest position written (size if nothing was inserted).
+__device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key,
+                          uint32_t *spos, int lane, int *first_ins) {
+    *first_ins = size;
+    key = wave_sort64(key, lane);
+    int m = __popcll(__ballot(key != KEY_NONE));
+    if (m == 0) return size;
+    int pos = 0;
+    bool dup = false;
+    if (lane < m) {
+        pos = lower_bound_pool(pool, size, key);
+        dup = pos < size && (pool[pos] & KEY_MASK) == key;
+    }
+    uint64_t dm = __ballot(dup);
+    if (dm) {
+        key = dup ? KEY_NONE : key;
+        key = wave_sort64(key, lane);
+        m -= __popcll(dm);
+        if (m == 0) return size;
+        pos = lane < m ? lower_bound_pool(pool, size, key) : 0;
+    }
+    // survivors that would land at or beyond Lcur are dropped by position
+    if (lane < m) spos[lane] = (uint32_t)pos;
+    wave_sync();
+    const int p0 = __shfl(pos, 0);
+    if (p0 >= Lcur) { *first_ins = size; return size; }
+    // shift pool entries [p0, size) right, from the back in chunks of 64
+    for (int top = size; top > p0; top -= 64) {
+        int i = top - 1 - lane;
+        bool act = i >= p0;
+        uint64_t v = 0;
+        int np = 0;
+        if (act) {
+            v = pool[i];
+            int lo = 0, hi = m;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if ((int)spos[mid] <= i) lo = mid + 1; else hi = mid;
+            }
+            np = i + lo;
+        }
+        wave_sync();
+        if (act && np < Lcur) pool[np] = v;
+        wave_sync();
+    }
+    if (lane < m) {
+        int np = pos + lane;
+        if (np < Lcur) pool[np] = key;
+    }
+    wave_sync();
+    *first_ins = p0;
+    int ns = size + m;
+    return ns < Lcur ? ns : Lcur;
+}
+
+// squared distances of q to the rows cid[0..cnt) (search format) -> cdist
+template <int DT, int LPR, int CPL>
+__device__ inline void gather_dist(const uint4 *rows, int row_chunks, const float (&qv)[CPL][Fmt<DT>::EPC],
+                                   const float (&sc)[CPL][Fmt<DT>::EPC],
+                                   const uint32_t *cid, float *cdist, int cnt, int lane) {
+    constexpr int EPC = Fmt<DT>::EPC;
+    constexpr int RPP = 64 / LPR;
+    constexpr int U = (8 / CPL) > 0 ? (8 / CPL) : 1;
+    const int g = lane / LPR, li = lane % LPR;
+    for (int r0 = 0; r0 < cnt; r0 += RPP * U) {
+        uint4 raw[U][CPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int r = r0 + u * RPP + g;
+            bool ok = r < cnt;
+            uint32_t id = ok ? cid[r] : 0u;
+            const uint4 *row = rows + (int64_t)id * row_chunks;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                int ch = li + c * LPR;
+                raw[u][c] = (ok && ch < row_chunks) ? row[ch] : make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                float x[EPC];
+                Fmt<DT>::dec(raw[u][c], x);
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) {
+                    float xv = DT == NSG_F32 ? x[e] : sc[c][e] * x[e];
+                    float t = qv[c][e] - xv;
+                    acc = fmaf(t, t, acc);
+                }
+            }
+#pragma unroll
+            for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            int r = r0 + u * RPP + g;
+            if (li == 0 && r < cnt) cdist[r] = acc;
+        }
+        if (r0 + RPP * U >= cnt) break;
+    }
+}
+
+
+}  // namespace nsg
