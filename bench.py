@@ -1,0 +1,264 @@
+"""Benchmark: QPS at recall@10 >= 0.95 on the SIFT-like 1M x 128 workload,
+plain FP32 search vs FP16 storage + learned early stop, on one MI355X.
+
+Pipeline (everything on the GPU through libnsg.so, outside the timed region):
+  data      seeded synthetic base (1M x 128), 10k test queries, 200k training queries
+  knn       exact 100-NN graph of the base (matrix-core brute force, self excluded)
+  build     NSG (Algorithm 2: R=50, l=40, C=500) on the GPU
+  truth     exact top-100 of the test queries (brute force)
+  sweep     plain FP32 search over L -> the smallest L with mean recall@10 >= 0.95
+  learned   traces on the FP16 index, labels, MLP training, calibration
+Timed: `--warmup` untimed steps, then `--steps` steps; a step is one search
+call over the whole 10k-query batch (queries already resident in HBM), for
+each of the two configurations.  Prints ONE JSON line.
+
+The CPU baseline is the oracle's Algorithm 1 (plain C, OpenMP over queries)
+on a bounded sample of the same queries, graph and L, on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+T0 = time.time()
+
+
+def log(msg):
+    print(f"[bench {time.time() - T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=0, help="override base size (development only)")
+    ap.add_argument("--train", type=int, default=200_000)
+    ap.add_argument("--target", type=float, default=0.95)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import datagen
+    import paper_1707_00143_amd as nsg
+    from paper_1707_00143_amd import learned_stop as ls
+
+    dev = torch.device("cuda:0")
+    w = datagen.SIFT1M_LIKE if not args.n else datagen.scaled(datagen.SIFT1M_LIKE, args.n)
+    k = 10
+
+    # ---------------- data ----------------
+    X = datagen.base(w)
+    Q = datagen.queries(w)
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    log(f"data {w.name}: base {X.shape}, queries {Q.shape}")
+
+    # ---------------- kNN graph + NSG build ----------------
+    torch.cuda.synchronize()
+    t = time.time()
+    knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
+    torch.cuda.synchronize()
+    t_knn = time.time() - t
+    log(f"knn graph K={w.K}: {t_knn:.2f}s")
+    t = time.time()
+    graph, nav, rep = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
+    torch.cuda.synchronize()
+    t_build = time.time() - t
+    del knn
+    deg = (graph != -1).sum(1).float()
+    log(f"NSG build: {t_build:.2f}s nav={nav} repair_edges={rep} AOD={deg.mean().item():.2f} "
+        f"MOD={int(deg.max().item())}")
+
+    truth, _ = nsg.knn_bruteforce(Xd, Qd, 100)
+    torch.cuda.synchronize()
+    log("ground truth top-100 of the test queries")
+
+    ix32 = nsg.load_index(Xd, graph, nav, "f32")
+    ix16 = nsg.load_index(Xd, graph, nav, "f16")
+    nq = Q.shape[0]
+
+    def recall(ids, kk=k):
+        h = nsg.recall_hits(ids.view(nq, 1, kk).contiguous(), truth, kk)
+        return h.float().mean().item() / kk
+
+    def min_L(ix, lo=10, hi=512):
+        found = None
+        for L in list(range(lo, 64, 2)) + list(range(64, 160, 4)) + list(range(160, hi + 1, 8)):
+            ids, _ = nsg.search(ix, Qd, k, L)
+            r = recall(ids)
+            if r >= args.target:
+                found = (L, r)
+                break
+        return found
+
+    # ---------------- sweep (recall@1/10/100 vs L, plain FP32) ----------------
+    sweep = []
+    for L in (10, 20, 40, 60, 100, 150, 200, 300):
+        ids, _ = nsg.search(ix32, Qd, 100, max(L, 100)) if L >= 100 else nsg.search(ix32, Qd, k, L)
+        r10 = recall(ids[:, :k].contiguous())
+        r1 = recall(ids[:, :1].contiguous(), 1)
+        r100 = recall(ids, 100) if ids.shape[1] == 100 else None
+        sweep.append(dict(L=L, r1=round(r1, 4), r10=round(r10, 4), r100=None if r100 is None else round(r100, 4)))
+    log(f"sweep FP32: {sweep}")
+    f32 = min_L(ix32)
+    f16 = min_L(ix16)
+    log(f"plain FP32: L={f32}; plain FP16+rerank: L={f16}")
+    if f32 is None:
+        print(json.dumps({"error": f"plain FP32 never reaches recall@10 {args.target}"}))
+        sys.exit(3)
+    L32 = f32[0]
+
+    # ---------------- learned early stop (FP16 index) ----------------
+    ntr = args.train
+    Tq = torch.from_numpy(datagen.train_queries(w, ntr)).to(dev)
+    ttruth, _ = nsg.knn_bruteforce(Xd, Tq, k)
+    t = time.time()
+    tr = ls.traces(ix16, Tq, ttruth, k=k)
+    torch.cuda.synchronize()
+    y, reached = ls.labels(tr, k)
+    log(f"traces: {ntr} queries x {len(tr.grid)} pool sizes in {time.time() - t:.1f}s; "
+        f"reached exact top-{k}: {reached.mean():.3f}")
+    n_fit = int(ntr * 0.9)
+    t = time.time()
+    P, mean, istd = ls.train(tr.features[:n_fit].contiguous(), y[:n_fit], seed=7, epochs=30,
+                             log=None)
+    torch.cuda.synchronize()
+    log(f"MLP trained in {time.time() - t:.1f}s")
+    yh = ls.predict(P, mean, istd, tr.features[n_fit:].contiguous()).cpu().numpy()
+    hold_mse = float(np.mean((yh - y[n_fit:]) ** 2))
+    base_mse = float(np.mean((y[n_fit:] - y[:n_fit].mean()) ** 2))
+    cal = ls.calibrate(yh, tr.hits[n_fit:].cpu().numpy(), tr.grid, k, args.target, margin=0.005)
+    log(f"held-out MSE {hold_mse:.4f} (constant predictor {base_mse:.4f}); calibration {cal}")
+    c = cal[0] if cal else 4.0
+    learned = None
+    L_fb = f16[0] if f16 else 512          # fixed-L fallback of the learned mode
+    for _ in range(12):
+        ls.install(ix16, P, mean, istd, c)
+        Lu = torch.empty(nq, dtype=torch.int32, device=dev)
+        ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L_fb, opts=dict(learned_stop=1, L_used=Lu))
+        r = recall(ids)
+        learned = dict(c=c, recall=r, mean_L=float(Lu.float().mean().item()))
+        if r >= args.target:
+            break
+        c *= 2 ** 0.25
+    log(f"learned stop on the test queries: {learned}")
+
+    # ---------------- timed region ----------------
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.time()
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+        ms = [a.elapsed_time(b) for a, b in ev]
+        return float(np.mean(ms)), wall
+
+    out32 = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), device=dev))
+    hops = torch.empty(nq, dtype=torch.int64, device=dev)
+    ndist = torch.empty(nq, dtype=torch.int64, device=dev)
+    nedge = torch.empty(nq, dtype=torch.int64, device=dev)
+
+    def step32():
+        nsg.search(ix32, Qd, k, L32, out_ids=out32[0], out_dist=out32[1])
+
+    ms32, wall32 = timed(step32, args.steps, args.warmup)
+    r32 = recall(out32[0])
+    out16 = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), device=dev))
+
+    def step16():
+        nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L_fb, out_ids=out16[0], out_dist=out16[1],
+                           opts=dict(learned_stop=1))
+
+    ms16, wall16 = timed(step16, args.steps, args.warmup)
+    r16 = recall(out16[0])
+    qps32 = nq / (ms32 / 1e3)
+    qps16 = nq / (ms16 / 1e3)
+    log(f"plain FP32 L={L32}: {ms32:.3f} ms/step, {qps32:,.0f} QPS, recall@10 {r32:.4f}")
+    log(f"FP16 + learned stop: {ms16:.3f} ms/step, {qps16:,.0f} QPS, recall@10 {r16:.4f}")
+
+    # ---------------- roofline of the dominant kernel (plain FP32 search) ----------------
+    nsg.search_batched(ix32, Qd, k_scalar=k, L_scalar=L32, opts=dict(hops=hops, ndist=ndist, nedges=nedge))
+    torch.cuda.synchronize()
+    d = X.shape[1]
+    H, N, E = hops.sum().item(), ndist.sum().item(), nedge.sum().item()
+    alg_bytes = N * d * 4 + (E + H) * 4 + nq * (d * 4 + k * 8)
+    achieved = alg_bytes / (ms32 / 1e3) / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=8000.0, unit="GB/s",
+                frac=round(achieved / 8000.0, 4), traffic=None,
+                kernel="search_kernel<F32,8,4>", bytes_per_launch=int(alg_bytes),
+                per_query=dict(hops=H / nq, ndist=N / nq, edges=E / nq))
+    log(f"roofline: {roof}")
+
+    # ---------------- CPU baseline: the oracle on a bounded sample ----------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        g_np = graph.cpu().numpy().view(np.uint32)
+        threads = len(os.sched_getaffinity(0))
+        m = 256
+        t = time.time()
+        oracle.search(X, g_np, nav, Q[:m], k, L32, threads=threads)
+        el = time.time() - t
+        m2 = int(min(nq, max(m, m * args.cpu_seconds / max(el, 1e-3))))
+        t = time.time()
+        o_ids, _, _, _ = oracle.search(X, g_np, nav, Q[:m2], k, L32, threads=threads)
+        el = time.time() - t
+        same = float(np.mean([set(a) == set(b) for a, b in zip(o_ids, out32[0][:m2].cpu().numpy().view(np.uint32))]))
+        cpu = dict(value=round(m2 / el, 1), unit="queries/s", cores=threads, kind="oracle",
+                   sample=f"first {m2} of {nq} test queries, plain Algorithm 1 at L={L32}, k={k}, "
+                          f"same graph; {el:.1f}s; GPU id sets equal on {same * 100:.1f}%")
+        log(f"cpu baseline: {cpu}")
+
+    res = {
+        "metric": "QPS at recall@10>=0.95, 1M x 128: FP16 storage + learned early stop (vs plain FP32)",
+        "value": round(qps16, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms16, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {X.shape[0]} x {d} float32 latent Gaussian mixture, {nq} queries, "
+                        f"NSG R={w.R} l={w.Lb} C={w.C} from exact {w.K}-NN graph; k={k}",
+            "plain_fp32": dict(L=L32, qps=round(qps32, 1), ms_per_step=round(ms32, 4), recall10=round(r32, 4)),
+            "fp16_learned": dict(qps=round(qps16, 1), recall10=round(r16, 4), **(learned or {})),
+            "plain_fp16_L": f16,
+            "speedup_vs_plain_fp32": round(qps16 / qps32, 3),
+            "index": dict(nav=nav, repair_edges=rep, aod=round(deg.mean().item(), 2), mod=int(deg.max().item()),
+                          knn_s=round(t_knn, 2), build_s=round(t_build, 2)),
+            "mlp": dict(heldout_mse=round(hold_mse, 4), const_mse=round(base_mse, 4)),
+            "sweep_fp32": sweep,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -25,7 +25,7 @@ class Workload:
     n_query: int
     n_comp: int
     seed: int
-    kind: str          # "iso" | "aniso_clip" | "norm_scaled" | "unit"
+    kind: str          # "iso" | "latent_clip" | "aniso_clip" | "norm_scaled" | "unit"
     # index parameters (Algorithm 2: K of the kNN graph, l = Lb, m = R, cap C)
     K: int = 100
     R: int = 50
@@ -36,9 +36,17 @@ class Workload:
 # Tiny: 10k x 128, 100-component isotropic mixture, means U[0,100], sigma U[2,8].
 TINY = Workload("tiny_10k_128", 10_000, 128, 100, 100, 1, "iso", K=100, R=50, Lb=40, C=500)
 # SIFT-like: 1M x 128, 1000-component anisotropic mixture, per-dim sigma U[1,10],
-# means U[0,255], clipped to [0,255].
-SIFT1M_LIKE = Workload("sift1m_like_1M_128", 1_000_000, 128, 10_000, 1000, 2, "aniso_clip",
+# clipped to [0,255].  The component means lie on a 10-dimensional linear
+# latent (128 + 5 * W z, z ~ N(0, I_10), W ~ N(0, 1/10)), so neighbouring
+# components overlap and the data form one connected cloud of low intrinsic
+# dimension, as descriptor data do.  (Means drawn independently U[0,255] give
+# 1000 isolated islands: the exact 100-NN graph then has no edge between
+# islands and a greedy search cannot cross them.)
+SIFT1M_LIKE = Workload("sift1m_like_1M_128", 1_000_000, 128, 10_000, 1000, 2, "latent_clip",
                        K=100, R=50, Lb=40, C=500)
+# the literal reading with independent U[0,255] means (kept for reference)
+SIFT1M_ISLANDS = Workload("sift1m_islands_1M_128", 1_000_000, 128, 10_000, 1000, 2, "aniso_clip",
+                          K=100, R=50, Lb=40, C=500)
 # GIST-like: 1M x 960, 500 components, L2-normalised then scaled by U[0.5, 2].
 GIST1M_LIKE = Workload("gist1m_like_1M_960", 1_000_000, 960, 1_000, 500, 3, "norm_scaled",
                        K=100, R=70, Lb=40, C=500)
@@ -62,6 +70,12 @@ def _mixture_params(w: Workload):
     elif w.kind == "aniso_clip":
         means = rng.uniform(0.0, 255.0, size=(c, d))
         sig = rng.uniform(1.0, 10.0, size=(c, d))
+    elif w.kind == "latent_clip":
+        m = 10
+        W = rng.normal(0.0, 1.0 / np.sqrt(m), size=(d, m))
+        z = rng.normal(0.0, 1.0, size=(c, m))
+        means = 128.0 + 5.0 * (z @ W.T)
+        sig = rng.uniform(1.0, 10.0, size=(c, d))
     elif w.kind in ("norm_scaled", "unit"):
         means = rng.normal(0.0, 1.0, size=(c, d))
         sig = rng.uniform(0.25, 1.0, size=(c, 1)) * np.ones((1, d))
@@ -78,7 +92,7 @@ def _draw(w: Workload, count: int, stream_seed: int, chunk: int = 1 << 16) -> np
         e = min(count, s + chunk)
         comp = rng.integers(0, w.n_comp, size=e - s)
         x = means[comp] + sig[comp] * rng.standard_normal(size=(e - s, w.d))
-        if w.kind == "aniso_clip":
+        if w.kind in ("aniso_clip", "latent_clip"):
             np.clip(x, 0.0, 255.0, out=x)
         elif w.kind == "norm_scaled":
             x /= np.maximum(np.linalg.norm(x, axis=1, keepdims=True), 1e-30)

@@ -117,10 +117,15 @@ typedef struct nsg_search_opts {
     int64_t *hops;           /* device [nq] expansions per query, or NULL */
     int64_t *ndist;          /* device [nq] distance evaluations per query, or NULL */
     int32_t *L_used;         /* device [nq] pool size after the early stop, or NULL */
-    float *features;         /* device [nq][d + 3] early-stop features at hop 16, or NULL */
+    float *features;         /* device [nq][d + 3] early-stop features (query, best pool
+                                distance, 1st/10th pool distance ratio, hops) right after
+                                expansion `feature_hop`; NaN rows for searches that ended
+                                earlier; or NULL */
     uint32_t *pool_ids;      /* device [nq][pool_stride] final pool ids, or NULL */
     float *pool_dist;        /* device [nq][pool_stride] final pool distances */
     int32_t pool_stride;
+    int32_t feature_hop;     /* hop at which `features` are taken (0: 16; the model's hop when learned) */
+    int64_t *nedges;         /* device [nq] valid neighbour entries read over all expansions, or NULL */
 } nsg_search_opts;
 
 /*
@@ -209,6 +214,14 @@ int nsg_mlp_adam(float *params, const float *grad, float *m, float *v,
 /* Forward only (inference), FP32: yhat[B]. */
 int nsg_mlp_forward(const float *params, int32_t in, int32_t h,
                     const float *X, int64_t B, float *yhat, void *stream);
+
+/*
+ * Per-column z-score statistics of X[B][in] (device): mean[in] and
+ * inv_std[in] = 1 / standard deviation (1 for a constant column).  Rows whose
+ * entry is NaN are skipped for that column.
+ */
+int nsg_column_stats(const float *X, int64_t B, int32_t in, float *mean,
+                     float *inv_std, void *stream);
 
 /*
  * Labels for training: for each query i and grid column j, the number of

@@ -47,6 +47,8 @@ class SearchOpts(ctypes.Structure):
         ("pool_ids", ctypes.c_void_p),
         ("pool_dist", ctypes.c_void_p),
         ("pool_stride", ctypes.c_int32),
+        ("feature_hop", ctypes.c_int32),
+        ("nedges", ctypes.c_void_p),
     ]
 
 
@@ -78,6 +80,7 @@ def _load():
         "nsg_mlp_adam": (i32, [P, P, P, P, i64, i64, f32, f32, f32, f32, P]),
         "nsg_mlp_forward": (i32, [P, i32, i32, P, i64, P, P]),
         "nsg_recall_hits": (i32, [P, i64, i32, i32, P, i32, P, P]),
+        "nsg_column_stats": (i32, [P, i64, i32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -278,6 +281,16 @@ def recall_hits(found, truth, k, stream=None):
     _call("nsg_recall_hits", _dev(found, torch.int32, "found"), nq, G, int(k), _dev(truth, torch.int32, "truth"),
           truth.shape[1], _dev(hits, torch.int32, "hits"), _stream(stream))
     return hits
+
+
+def column_stats(X, stream=None):
+    """nsg_column_stats: (mean [in], inv_std [in]) of X [B][in]."""
+    B, n_in = X.shape
+    mean = torch.empty(n_in, dtype=torch.float32, device=X.device)
+    istd = torch.empty(n_in, dtype=torch.float32, device=X.device)
+    _call("nsg_column_stats", _dev(X, torch.float32, "X"), B, n_in, _dev(mean, torch.float32, "mean"),
+          _dev(istd, torch.float32, "inv_std"), _stream(stream))
+    return mean, istd
 
 
 _load()

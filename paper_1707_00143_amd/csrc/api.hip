@@ -305,7 +305,7 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     if (o.waves_per_block < 0 || o.waves_per_block > 16) return fail(NSG_EINVAL, "waves_per_block out of range");
     if (o.pool_ids && (o.pool_stride < 1 || !o.pool_dist)) return fail(NSG_EINVAL, "pool output needs stride and dist");
     if (o.learned_stop && !stop_ready(idx)) return fail(NSG_ESTATE, "no early-stop model loaded and enabled");
-    if (o.features && !o.learned_stop) return fail(NSG_EINVAL, "features need learned_stop");
+    if (o.feature_hop < 0) return fail(NSG_EINVAL, "feature_hop < 0");
     if (nq == 0) return NSG_OK;
     SearchArgs a{};
     a.idx = idx;
@@ -331,6 +331,8 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.ndist = o.ndist;
     a.L_used = o.L_used;
     a.features = o.features;
+    a.feature_hop = o.feature_hop;
+    a.nedges = o.nedges;
     a.pool_ids = o.pool_ids;
     a.pool_dist = o.pool_dist;
     a.pool_stride = o.pool_stride;

@@ -81,6 +81,8 @@ struct SearchArgs {
     int32_t learned;
     int64_t *hops;
     int64_t *ndist;
+    int64_t *nedges;          // valid neighbour entries read, summed over expansions
+    int32_t feature_hop;      // decision / trace hop (0: 16)
     int32_t *L_used;
     float *features;
     uint32_t *pool_ids;

@@ -169,6 +169,29 @@ __global__ void recall_hits_kernel(const uint32_t *found, int64_t nq, int G, int
     hits[t] = c;
 }
 
+// per-column mean and 1/std (FP64 sums; std floored at 1e-12 of the mean
+// magnitude and 1e-30), one thread per column, rows in order (deterministic).
+// NaN rows (searches that ended before the feature hop) are skipped.
+__global__ void column_stats_kernel(const float *X, int64_t B, int in, float *mean, float *inv_std) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= in) return;
+    double s = 0.0, s2 = 0.0;
+    int64_t c = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        float v = X[b * in + j];
+        if (isnan(v)) continue;
+        s += v;
+        s2 += (double)v * v;
+        ++c;
+    }
+    double m = c ? s / (double)c : 0.0;
+    double var = c ? s2 / (double)c - m * m : 0.0;
+    double sd = sqrt(var > 0.0 ? var : 0.0);
+    double floor_ = fmax(1e-12 * fabs(m), 1e-30);
+    mean[j] = (float)m;
+    inv_std[j] = (float)(1.0 / (sd > floor_ ? sd : 1.0));
+}
+
 static int mlp_rows(const float *params, int in, int h, const float *X, const float *y, int64_t B, float *yhat,
                     float *ws, hipStream_t st) {
     MlpRows r{};
@@ -253,6 +276,16 @@ extern "C" int nsg_recall_hits(const uint32_t *found, int64_t nq, int32_t G, int
     int64_t t = nq * G;
     hipLaunchKernelGGL(recall_hits_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                        found, nq, G, k, truth, k_truth, hits);
+    NSG_HIP(hipGetLastError());
+    return NSG_OK;
+}
+
+extern "C" int nsg_column_stats(const float *X, int64_t B, int32_t in, float *mean, float *inv_std, void *stream) {
+    clear_error();
+    if (!X || !mean || !inv_std) return fail(NSG_EINVAL, "NULL pointer");
+    if (B < 1 || in < 1) return fail(NSG_EINVAL, "bad shape");
+    hipLaunchKernelGGL(column_stats_kernel, dim3((in + 255) / 256), dim3(256), 0, (hipStream_t)stream, X, B, in,
+                       mean, inv_std);
     NSG_HIP(hipGetLastError());
     return NSG_OK;
 }

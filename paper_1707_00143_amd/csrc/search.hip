@@ -31,7 +31,7 @@ struct KParams {
     int L_cap, L_alloc, hash_bits, lds_per_wave, feat_cap;
     int rerank;
     unsigned int *counter;
-    int64_t *hops, *ndist;
+    int64_t *hops, *ndist, *nedges;
     int32_t *L_used;
     float *features;
     uint32_t *pool_ids;
@@ -103,11 +103,12 @@ __device__ inline void lds_sort(uint64_t *a, int n, int cap, int lane) {
     }
 }
 
-// learned early stop: features -> MLP (FP16 weights, FP32 accumulate) -> L_hat
-__device__ inline int stop_predict(const KParams &p, const float *q, const uint64_t *pool,
-                                   int size, int64_t hops, int Lq, int kq, float *xbuf,
-                                   int lane, int64_t qi) {
-    const int in = p.s_in, h = p.s_h;
+// early-stop features after the decision expansion: the query, the best pool
+// distance, the ratio of the 1st to the 10th pool distance, the hop count.
+// Written raw to p.features (if given) and z-scored into xbuf (if learned).
+__device__ inline void stop_features(const KParams &p, const float *q, const uint64_t *pool,
+                                     int size, int64_t hops, float *xbuf, int lane, int64_t qi) {
+    const int in = p.d + 3;
     const float d0 = key_dist(pool[0]);
     const float d9 = key_dist(pool[size > 10 ? 9 : size - 1]);
     for (int i = lane; i < in; i += 64) {
@@ -117,9 +118,15 @@ __device__ inline int stop_predict(const KParams &p, const float *q, const uint6
         else if (i == p.d + 1) f = d9 > 0.0f ? d0 / d9 : 1.0f;
         else f = (float)hops;
         if (p.features) p.features[qi * (int64_t)in + i] = f;
-        xbuf[i] = (f - p.stop_f32[i]) * p.stop_f32[in + i];
+        if (p.learned) xbuf[i] = (f - p.stop_f32[i]) * p.stop_f32[in + i];
     }
     wave_sync();
+}
+
+// learned early stop: z-scored features in xbuf -> MLP (FP16 weights, FP32
+// accumulate) -> y = log2 pool size -> L_hat on the grid
+__device__ inline int stop_predict(const KParams &p, int Lq, int kq, const float *xbuf, int lane) {
+    const int in = p.s_in, h = p.s_h;
     const float *b1 = p.stop_f32 + 2 * in;
     const float *b2 = b1 + h;
     const float b3 = b2[h];
@@ -214,7 +221,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
         wave_sync();
 
         const uint32_t start = p.start;
-        int64_t hops = 0, nd = 0;
+        int64_t hops = 0, nd = 0, ne = 0;
         int vcount = 0;
         int size = 0;
         const bool rec = p.vis_ids != nullptr;
@@ -234,7 +241,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
         size = 1;
         wave_sync();
         int cursor = 0;
-        bool stopped = !learned;   // true once the early-stop decision was taken
+        bool stopped = !learned && !p.features;   // true once the decision hop has passed
 
         for (;;) {
             int i = find_unchecked(pool, cursor, size, lane);
@@ -250,6 +257,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
             for (int b = 0; b < p.R; b += 64) {
                 int j = b + lane;
                 uint32_t u = j < p.R ? grow[j] : NSG_SENT;
+                ne += __popcll(__ballot(u != NSG_SENT));
                 bool nw = u != NSG_SENT && hash_insert(hash, p.hash_bits, u);
                 uint64_t bm = __ballot(nw);
                 int rank = __popcll(bm & ((1ull << lane) - 1ull));
@@ -289,17 +297,22 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
             }
             if (!stopped && hops >= p.s_hop) {
                 stopped = true;
-                int Lh = stop_predict(p, q, pool, size, hops, Lq, kq, xbuf, lane, qi);
-                Lcur = Lh;
-                if (size > Lcur) size = Lcur;
-                if (cursor > size) cursor = size;
+                stop_features(p, q, pool, size, hops, xbuf, lane, qi);
+                if (learned) {
+                    Lcur = stop_predict(p, Lq, kq, xbuf, lane);
+                    if (size > Lcur) size = Lcur;
+                    if (cursor > size) cursor = size;
+                }
             }
         }
-        if (learned && !stopped) {
+        if (!stopped) {
             // ended before the decision point: the result equals the plain one
-            if (p.features) for (int t = lane; t < p.s_in; t += 64) p.features[qi * (int64_t)p.s_in + t] = NAN;
-            Lcur = Lq;
-            if (size > Lcur) size = Lcur;
+            if (p.features)
+                for (int t = lane; t < p.d + 3; t += 64) p.features[qi * (int64_t)(p.d + 3) + t] = NAN;
+            if (learned) {
+                Lcur = Lq;
+                if (size > Lcur) size = Lcur;
+            }
         }
         if (p.self_offset >= 0) {
             // index build: also visit the query node's own row (its kNN list)
@@ -348,6 +361,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
         if (lane == 0) {
             if (p.hops) p.hops[qi] = hops;
             if (p.ndist) p.ndist[qi] = nd;
+            if (p.nedges) p.nedges[qi] = ne;
             if (p.L_used) p.L_used[qi] = Lcur;
             if (p.vis_cnt) p.vis_cnt[qi] = vcount;
         }
@@ -416,6 +430,7 @@ int launch_search(const SearchArgs &a) {
     p.rerank = a.rerank;
     p.hops = a.hops;
     p.ndist = a.ndist;
+    p.nedges = a.nedges;
     p.L_used = a.L_used;
     p.features = a.features;
     p.pool_ids = a.pool_ids;
@@ -427,7 +442,9 @@ int launch_search(const SearchArgs &a) {
     p.vis_cap = a.vis_cap;
     p.self_offset = a.self_offset;
     p.learned = 0;
-    p.feat_cap = 0;
+    p.feat_cap = a.features ? ((ix->d + 3 + 3) & ~3) : 0;
+    p.s_in = ix->d + 3;
+    p.s_hop = a.feature_hop > 0 ? a.feature_hop : 16;
     if (a.learned) {
         const StopModel &sm = ix->stop;
         p.learned = 1;
@@ -440,6 +457,8 @@ int launch_search(const SearchArgs &a) {
         p.grid_n = sm.grid_n;
         p.calib_c = sm.calib_c;
         p.feat_cap = (sm.in + 3) & ~3;
+        if (a.features && sm.hop != p.s_hop && a.feature_hop > 0)
+            return fail(NSG_EINVAL, "feature hop differs from the model's decision hop");
     }
     int L_alloc = 1;
     while (L_alloc < a.L_cap) L_alloc <<= 1;

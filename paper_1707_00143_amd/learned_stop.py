@@ -1,0 +1,154 @@
+"""Learned early termination: traces, labels, training and calibration.
+
+Driver around the library's kernels (an extension of the method; the paper
+has no early stop).  For every training query the plain search is run at each
+pool size of a geometric grid (16 .. 512 in 2^(1/4) steps); the label is
+log2 of the smallest grid L whose top-k equals the exact top-k (queries that
+never reach it are censored at 512).  Features are taken after the 16th
+expansion, where every run with L >= 16 has made the same expansions, so one
+capture serves every grid point.  The network (d+3 -> 64 -> 64 -> 1, ReLU) is
+trained with the library's forward/backward and Adam kernels on z-scored
+features; the calibration constant c is the smallest one whose held-out mean
+recall meets the target when the pool is cut to the grid value at or above
+c * 2^y.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import (column_stats, load_stop_model, mlp_adam, mlp_forward, mlp_forward_backward, recall_hits,
+               search_batched, set_stop_mode)
+
+GRID = [int(round(16 * 2 ** (i / 4))) for i in range(21)]   # 16, 19, 23, ..., 512
+HOP = 16
+HIDDEN = 64
+
+
+@dataclasses.dataclass
+class Traces:
+    features: torch.Tensor   # [nq][d+3] float32 (NaN rows: search ended before the hop)
+    hits: torch.Tensor       # [nq][G] int32: |top-k at grid L ∩ exact top-k|
+    grid: list
+
+
+def traces(index, queries, truth, k=10, grid=GRID, chunk=50_000):
+    """Plain search at every grid L; features at HOP from the first run."""
+    nq, d = queries.shape
+    dev = queries.device
+    feats = torch.empty((nq, d + 3), dtype=torch.float32, device=dev)
+    hits = torch.empty((nq, len(grid)), dtype=torch.int32, device=dev)
+    found = torch.empty((min(chunk, nq), len(grid), k), dtype=torch.int32, device=dev)
+    for s in range(0, nq, chunk):
+        e = min(nq, s + chunk)
+        q = queries[s:e]
+        for g, L in enumerate(grid):
+            ids = torch.empty((e - s, k), dtype=torch.int32, device=dev)
+            dist = torch.empty((e - s, k), dtype=torch.float32, device=dev)
+            opts = dict(features=feats[s:e], feature_hop=HOP) if g == 0 else None
+            search_batched(index, q, k_scalar=k, L_scalar=L, out_ids=ids, out_dist=dist, opts=opts)
+            found[:e - s, g].copy_(ids)
+        hits[s:e] = recall_hits(found[:e - s].contiguous(), truth[s:e].contiguous(), k)
+    return Traces(feats, hits, list(grid))
+
+
+def labels(tr: Traces, k=10):
+    """y = log2 of the smallest grid L reaching the exact top-k (censored at the top)."""
+    h = tr.hits.cpu().numpy()
+    ok = h >= k
+    first = np.where(ok.any(1), ok.argmax(1), len(tr.grid) - 1)
+    L = np.asarray(tr.grid)[first]
+    return np.log2(L).astype(np.float32), ok.any(1)
+
+
+def init_params(n_in, h, seed):
+    """He-uniform weights, zero biases (layout W1, b1, W2, b2, W3, b3)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((n_in, h), (h, h), (h, 1)):
+        lim = np.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(features, y, seed=0, epochs=30, batch=1024, lr=1e-3, log=None):
+    """Adam on MSE; returns (params, mean, inv_std) as device tensors."""
+    dev = features.device
+    keep = ~torch.isnan(features).any(1)
+    X = features[keep].contiguous()
+    yy = torch.from_numpy(y).to(dev)[keep].contiguous()
+    n, n_in = X.shape
+    mean, istd = column_stats(X)
+    Xz = ((X - mean) * istd).contiguous()
+    P = torch.from_numpy(init_params(n_in, HIDDEN, seed)).to(dev)
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    grad = torch.empty_like(P)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(seed + 1)
+    t = 0
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).to(dev)
+        Xp = Xz.index_select(0, perm)
+        yp = yy.index_select(0, perm)
+        tot = 0.0
+        nb = 0
+        for s in range(0, n - batch + 1, batch):
+            t += 1
+            mlp_forward_backward(P, n_in, HIDDEN, Xp[s:s + batch], yp[s:s + batch], grad=grad, loss=loss)
+            mlp_adam(P, grad, m, v, t, lr=lr)
+            if log is not None and s == 0:
+                tot += float(loss.item())
+                nb += 1
+        if log is not None:
+            log(f"  epoch {ep}: loss {tot / max(nb, 1):.4f}")
+    return P, mean, istd
+
+
+def predict(P, mean, istd, features):
+    Xz = ((features - mean) * istd).contiguous()
+    Xz = torch.nan_to_num(Xz, nan=0.0)
+    return mlp_forward(P, Xz.shape[1], HIDDEN, Xz)
+
+
+def l_hat(yhat, c, grid, k=10):
+    """Pool size the kernel picks: smallest grid value >= c * 2^y, clamped."""
+    t = c * np.exp2(np.asarray(yhat, np.float64))
+    g = np.asarray(grid, np.float64)
+    idx = np.searchsorted(g, t, side="left")
+    idx = np.clip(idx, 0, len(g) - 1)
+    L = g[idx]
+    L = np.maximum(L, max(16, k))
+    return np.where(np.isfinite(t), L, np.nan)
+
+
+def calibrate(yhat, hits, grid, k=10, target=0.95, margin=0.0):
+    """Smallest c (on a 2^(1/16) ladder) whose mean held-out recall >= target."""
+    yhat = np.asarray(yhat)
+    h = np.asarray(hits)
+    g = np.asarray(grid)
+    best = None
+    for j in range(-64, 97):
+        c = 2.0 ** (j / 16)
+        L = l_hat(yhat, c, grid, k)
+        col = np.searchsorted(g, L)
+        col = np.clip(col, 0, len(g) - 1)
+        rec = h[np.arange(len(h)), col] / k
+        if rec.mean() >= target + margin:
+            best = (c, float(rec.mean()), float(L.mean()))
+            break
+    return best
+
+
+def model_blob(P, mean, istd, grid):
+    parts = [mean.cpu().numpy(), istd.cpu().numpy(), P.cpu().numpy(), np.asarray(grid, np.float32)]
+    return np.concatenate([p.astype(np.float32).ravel() for p in parts]).tobytes()
+
+
+def install(index, P, mean, istd, c, grid=GRID):
+    n_in = mean.numel()
+    load_stop_model(index, model_blob(P, mean, istd, grid), n_in, HIDDEN, HOP, len(grid))
+    set_stop_mode(index, True, c)

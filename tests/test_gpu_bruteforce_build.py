@@ -39,7 +39,11 @@ def test_bruteforce_matches_exact_knn(nsg, n, d, nq, k):
     assert r["ok"], r
     # ordering: ascending distance
     dd = dist.cpu().numpy()
+    fin = np.isfinite(dd)
+    assert (fin[:, :-1] >= fin[:, 1:]).all()                # padding only at the tail
+    dd = np.where(fin, dd, np.float32(3e38))
     assert (np.diff(dd, axis=1) >= 0).all()
+    assert ((ids.cpu().numpy() == -1) == ~fin).all()
 
 
 def test_bruteforce_knn_graph_tiny(nsg, tiny_index):
