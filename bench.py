@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cache", default="", help="directory: reuse (or save) the graph, L and model of a "
+                                                 "previous run of the same workload (profiling passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -68,17 +70,26 @@ def main():
     log(f"data {w.name}: base {X.shape}, queries {Q.shape}")
 
     # ---------------- kNN graph + NSG build ----------------
+    cache = os.path.join(args.cache, f"{w.name}.npz") if args.cache else ""
+    cached = np.load(cache) if cache and os.path.exists(cache) else None
     torch.cuda.synchronize()
-    t = time.time()
-    knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
-    torch.cuda.synchronize()
-    t_knn = time.time() - t
-    log(f"knn graph K={w.K}: {t_knn:.2f}s")
-    t = time.time()
-    graph, nav, rep = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
-    torch.cuda.synchronize()
-    t_build = time.time() - t
-    del knn
+    if cached is not None:
+        graph = torch.from_numpy(cached["graph"]).to(dev)
+        nav, rep = int(cached["nav"]), int(cached["rep"])
+        t_knn = float(cached["t_knn"])
+        t_build = float(cached["t_build"])
+        log(f"graph from cache {cache}")
+    else:
+        t = time.time()
+        knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
+        torch.cuda.synchronize()
+        t_knn = time.time() - t
+        log(f"knn graph K={w.K}: {t_knn:.2f}s")
+        t = time.time()
+        graph, nav, rep = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
+        torch.cuda.synchronize()
+        t_build = time.time() - t
+        del knn
     deg = (graph != -1).sum(1).float()
     log(f"NSG build: {t_build:.2f}s nav={nav} repair_edges={rep} AOD={deg.mean().item():.2f} "
         f"MOD={int(deg.max().item())}")
@@ -106,6 +117,9 @@ def main():
         return found
 
     # ---------------- sweep (recall@1/10/100 vs L, plain FP32) ----------------
+    if cached is not None:
+        return run_timed(args, cached, nsg, ls, torch, dev, w, X, Q, Xd, Qd, ix32, ix16, graph, nav, rep,
+                         deg, truth, k, t_knn, t_build)
     sweep = []
     for L in (10, 20, 40, 60, 100, 150, 200, 300):
         ids, _ = nsg.search(ix32, Qd, 100, max(L, 100)) if L >= 100 else nsg.search(ix32, Qd, k, L)
@@ -156,6 +170,37 @@ def main():
             break
         c *= 2 ** 0.25
     log(f"learned stop on the test queries: {learned}")
+    if cache:
+        os.makedirs(args.cache, exist_ok=True)
+        np.savez(cache, graph=graph.cpu().numpy(), nav=nav, rep=rep, t_knn=t_knn, t_build=t_build, L32=L32,
+                 L_fb=L_fb, c=c, P=P.cpu().numpy(), mean=mean.cpu().numpy(), istd=istd.cpu().numpy(),
+                 f16=np.asarray(f16 if f16 else (0, 0.0)), hold_mse=hold_mse, base_mse=base_mse,
+                 sweep=json.dumps(sweep), learned=json.dumps(learned))
+        log(f"saved {cache}")
+    return finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn,
+                  t_build, L32, L_fb, f16, learned, hold_mse, base_mse, sweep)
+
+
+def run_timed(args, z, nsg, ls, torch, dev, w, X, Q, Xd, Qd, ix32, ix16, graph, nav, rep, deg, truth, k,
+              t_knn, t_build):
+    """Timed part only, with L, model and calibration from a cached run."""
+    P = torch.from_numpy(z["P"]).to(dev)
+    mean = torch.from_numpy(z["mean"]).to(dev)
+    istd = torch.from_numpy(z["istd"]).to(dev)
+    ls.install(ix16, P, mean, istd, float(z["c"]))
+    f16 = tuple(z["f16"].tolist()) if z["f16"][0] else None
+    return finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn,
+                  t_build, int(z["L32"]), int(z["L_fb"]), f16, json.loads(str(z["learned"])),
+                  float(z["hold_mse"]), float(z["base_mse"]), json.loads(str(z["sweep"])))
+
+
+def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn, t_build,
+           L32, L_fb, f16, learned, hold_mse, base_mse, sweep):
+    nq = Q.shape[0]
+
+    def recall(ids, kk=k):
+        h = nsg.recall_hits(ids.view(nq, 1, kk).contiguous(), truth, kk)
+        return h.float().mean().item() / kk
 
     # ---------------- timed region ----------------
     def timed(fn, steps, warm):

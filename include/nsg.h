@@ -126,6 +126,9 @@ typedef struct nsg_search_opts {
     int32_t pool_stride;
     int32_t feature_hop;     /* hop at which `features` are taken (0: 16; the model's hop when learned) */
     int64_t *nedges;         /* device [nq] valid neighbour entries read over all expansions, or NULL */
+    int32_t lanes_per_row;   /* lanes that gather one row (8, 16, 32, 64); 0: default */
+    uint32_t *counter;       /* device scratch word for the persistent work counter (reset by the
+                                call); NULL: allocated per call (not usable under graph capture) */
 } nsg_search_opts;
 
 /*
@@ -140,6 +143,38 @@ int nsg_search_batched(const nsg_index *idx, const float *queries, int64_t nq,
                        int32_t k_scalar, int32_t L_scalar, int32_t out_stride,
                        uint32_t *out_ids, float *out_dist,
                        const nsg_search_opts *opts, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batches as HIP graphs, and the launch autotuner                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct nsg_search_graph nsg_search_graph;   /* opaque, owned by the library */
+
+/*
+ * Capture one nsg_search_batched call (same arguments) into a HIP graph and
+ * instantiate it.  The buffers are bound at capture: refill `queries` (and
+ * k / L) in place, then nsg_search_graph_launch replays the whole batch with
+ * one launch.  With opts->persistent the graph owns its work counter.
+ */
+int nsg_search_graph_create(const nsg_index *idx, const float *queries, int64_t nq,
+                            const int32_t *k, const int32_t *L, int32_t k_scalar,
+                            int32_t L_scalar, int32_t out_stride, uint32_t *out_ids,
+                            float *out_dist, const nsg_search_opts *opts,
+                            nsg_search_graph **out);
+int nsg_search_graph_launch(nsg_search_graph *g, void *stream);
+void nsg_search_graph_destroy(nsg_search_graph *g);   /* NULL-safe; synchronises */
+
+/*
+ * Time candidate launch configurations of nsg_search_batched (lanes per row,
+ * waves per block, visited-filter size, persistent grid) on the given batch
+ * (scalar k, L) and return the fastest in *best (host; other fields zeroed)
+ * with its mean time per call in *best_ms (host).  `trials` timed calls per
+ * candidate after one warm-up.  Synchronous; writes no caller memory except
+ * *best and *best_ms.
+ */
+int nsg_autotune(const nsg_index *idx, const float *queries, int64_t nq, int32_t k,
+                 int32_t L, int32_t trials, nsg_search_opts *best, float *best_ms,
+                 void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Exact K nearest neighbours (serial scan, Sec. 4.1.2 item 1; K-NNS, Sec. 2.1) */

@@ -49,6 +49,8 @@ class SearchOpts(ctypes.Structure):
         ("pool_stride", ctypes.c_int32),
         ("feature_hop", ctypes.c_int32),
         ("nedges", ctypes.c_void_p),
+        ("lanes_per_row", ctypes.c_int32),
+        ("counter", ctypes.c_void_p),
     ]
 
 
@@ -81,6 +83,11 @@ def _load():
         "nsg_mlp_forward": (i32, [P, i32, i32, P, i64, P, P]),
         "nsg_recall_hits": (i32, [P, i64, i32, i32, P, i32, P, P]),
         "nsg_column_stats": (i32, [P, i64, i32, P, P, P]),
+        "nsg_search_graph_create": (i32, [P, P, i64, P, P, i32, i32, i32, P, P, ctypes.POINTER(SearchOpts),
+                                          ctypes.POINTER(P)]),
+        "nsg_search_graph_launch": (i32, [P, P]),
+        "nsg_search_graph_destroy": (None, [P]),
+        "nsg_autotune": (i32, [P, P, i64, i32, i32, i32, ctypes.POINTER(SearchOpts), ctypes.POINTER(f32), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -192,17 +199,7 @@ def search_batched(index: Index, queries, k=None, L=None, k_scalar=10, L_scalar=
         out_ids = torch.full((nq, out_stride), SENT, dtype=torch.int32, device=queries.device)
     if out_dist is None:
         out_dist = torch.full((nq, out_stride), float("inf"), dtype=torch.float32, device=queries.device)
-    o = SearchOpts()
-    o.rerank = -1
-    keep = []
-    for key, val in (opts or {}).items():
-        if isinstance(val, torch.Tensor):
-            if not val.is_cuda or not val.is_contiguous():
-                raise ValueError(f"opts[{key}] must be a contiguous CUDA tensor")
-            keep.append(val)
-            setattr(o, key, val.data_ptr())
-        else:
-            setattr(o, key, int(val))
+    o, keep = _opts(opts)
     _call("nsg_search_batched", index.handle, _dev(queries, torch.float32, "queries"), nq,
           _dev(k, torch.int32, "k"), _dev(L, torch.int32, "L"), int(k_scalar), int(L_scalar), int(out_stride),
           _dev(out_ids, torch.int32, "out_ids"), _dev(out_dist, torch.float32, "out_dist"), ctypes.byref(o),
@@ -281,6 +278,69 @@ def recall_hits(found, truth, k, stream=None):
     _call("nsg_recall_hits", _dev(found, torch.int32, "found"), nq, G, int(k), _dev(truth, torch.int32, "truth"),
           truth.shape[1], _dev(hits, torch.int32, "hits"), _stream(stream))
     return hits
+
+
+def _opts(opts):
+    o = SearchOpts()
+    o.rerank = -1
+    keep = []
+    for key, val in (opts or {}).items():
+        if isinstance(val, torch.Tensor):
+            if not val.is_cuda or not val.is_contiguous():
+                raise ValueError(f"opts[{key}] must be a contiguous CUDA tensor")
+            keep.append(val)
+            setattr(o, key, val.data_ptr())
+        else:
+            setattr(o, key, int(val))
+    return o, keep
+
+
+class SearchGraph:
+    """nsg_search_graph_*: one batch captured as a HIP graph; refill the bound
+    input tensors in place and call launch()."""
+
+    def __init__(self, index, queries, k=None, L=None, k_scalar=10, L_scalar=None, out_stride=None,
+                 opts: dict | None = None):
+        nq = queries.shape[0]
+        if out_stride is None:
+            out_stride = int(k_scalar) if k is None else int(k.max().item())
+        self.queries, self.k, self.L = queries, k, L
+        self.out_ids = torch.full((nq, out_stride), SENT, dtype=torch.int32, device=queries.device)
+        self.out_dist = torch.full((nq, out_stride), float("inf"), dtype=torch.float32, device=queries.device)
+        o, self._keep = _opts(opts)
+        h = ctypes.c_void_p()
+        _call("nsg_search_graph_create", index.handle, _dev(queries, torch.float32, "queries"), nq,
+              _dev(k, torch.int32, "k"), _dev(L, torch.int32, "L"), int(k_scalar), int(L_scalar), int(out_stride),
+              _dev(self.out_ids, torch.int32, "out_ids"), _dev(self.out_dist, torch.float32, "out_dist"),
+              ctypes.byref(o), ctypes.byref(h))
+        self._h = h
+        self._index = index
+
+    def launch(self, stream=None):
+        _call("nsg_search_graph_launch", self._h, _stream(stream))
+        return self.out_ids, self.out_dist
+
+    def close(self):
+        if self._h is not None:
+            _load().nsg_search_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(index, queries, k, L, trials=3, stream=None):
+    """nsg_autotune: returns (opts dict for search_batched, ms per call)."""
+    o = SearchOpts()
+    ms = ctypes.c_float()
+    _call("nsg_autotune", index.handle, _dev(queries, torch.float32, "queries"), queries.shape[0], int(k), int(L),
+          int(trials), ctypes.byref(o), ctypes.byref(ms), _stream(stream))
+    best = dict(lanes_per_row=o.lanes_per_row, hash_slots=o.hash_slots, waves_per_block=o.waves_per_block,
+                persistent=o.persistent)
+    return best, float(ms.value)
 
 
 def column_stats(X, stream=None):

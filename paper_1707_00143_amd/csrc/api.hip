@@ -306,6 +306,10 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     if (o.pool_ids && (o.pool_stride < 1 || !o.pool_dist)) return fail(NSG_EINVAL, "pool output needs stride and dist");
     if (o.learned_stop && !stop_ready(idx)) return fail(NSG_ESTATE, "no early-stop model loaded and enabled");
     if (o.feature_hop < 0) return fail(NSG_EINVAL, "feature_hop < 0");
+    if (o.lanes_per_row && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
+        o.lanes_per_row != 64)
+        return fail(NSG_EINVAL, "lanes_per_row must be 0, 8, 16, 32 or 64");
+    if (o.blocks < 0) return fail(NSG_EINVAL, "blocks < 0");
     if (nq == 0) return NSG_OK;
     SearchArgs a{};
     a.idx = idx;
@@ -333,6 +337,8 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.features = o.features;
     a.feature_hop = o.feature_hop;
     a.nedges = o.nedges;
+    a.lanes_per_row = o.lanes_per_row;
+    a.counter = o.counter;
     a.pool_ids = o.pool_ids;
     a.pool_dist = o.pool_dist;
     a.pool_stride = o.pool_stride;
@@ -406,5 +412,147 @@ extern "C" int nsg_set_stop_mode(nsg_index *idx, int32_t enabled, float calib_c)
     if (!(calib_c > 0.0f) || !std::isfinite(calib_c)) return fail(NSG_EINVAL, "calibration must be finite and > 0");
     idx->stop.enabled = enabled ? 1 : 0;
     idx->stop.calib_c = calib_c;
+    return NSG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches as HIP graphs
+// ---------------------------------------------------------------------------
+struct nsg_search_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned int *counter = nullptr;
+};
+
+extern "C" void nsg_search_graph_destroy(nsg_search_graph *g) {
+    if (!g) return;
+    hipDeviceSynchronize();
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    hipFree(g->counter);
+    delete g;
+}
+
+extern "C" int nsg_search_graph_create(const nsg_index *idx, const float *queries, int64_t nq, const int32_t *k,
+                                       const int32_t *L, int32_t k_scalar, int32_t L_scalar, int32_t out_stride,
+                                       uint32_t *out_ids, float *out_dist, const nsg_search_opts *opts,
+                                       nsg_search_graph **out) {
+    clear_error();
+    if (!out) return fail(NSG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nq < 1) return fail(NSG_EINVAL, "a captured batch needs nq >= 1");
+    nsg_search_graph *g = new nsg_search_graph();
+    nsg_search_opts o{};
+    if (opts) o = *opts;
+    else o.rerank = -1;
+    if (o.persistent && !o.counter) {
+        if (hipMalloc(&g->counter, sizeof(unsigned int) * 64) != hipSuccess) {
+            delete g;
+            return fail(NSG_ENOMEM, "counter allocation failed");
+        }
+        o.counter = g->counter;
+    }
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        nsg_search_graph_destroy(g);
+        return fail(NSG_EDEVICE, "stream creation failed");
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    int rc = NSG_OK;
+    if (e == hipSuccess) {
+        rc = nsg_search_batched(idx, queries, nq, k, L, k_scalar, L_scalar, out_stride, out_ids, out_dist, &o, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+        if (rc == NSG_OK && e2 != hipSuccess) rc = fail(NSG_EDEVICE, "capture failed: %s", hipGetErrorString(e2));
+    } else {
+        rc = fail(NSG_EDEVICE, "begin capture failed: %s", hipGetErrorString(e));
+    }
+    if (rc == NSG_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail(NSG_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    hipStreamDestroy(cs);
+    if (rc != NSG_OK) {
+        nsg_search_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return NSG_OK;
+}
+
+extern "C" int nsg_search_graph_launch(nsg_search_graph *g, void *stream) {
+    clear_error();
+    if (!g || !g->exec) return fail(NSG_EINVAL, "graph is NULL");
+    NSG_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return NSG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: time launch configurations on the caller's batch
+// ---------------------------------------------------------------------------
+extern "C" int nsg_autotune(const nsg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
+                            int32_t trials, nsg_search_opts *best, float *best_ms, void *stream) {
+    clear_error();
+    if (!idx || !queries || !best || !best_ms) return fail(NSG_EINVAL, "NULL pointer");
+    if (nq < 1 || k < 1 || k > kMaxK || L < 1 || L > kMaxL || trials < 1) return fail(NSG_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *ids = nullptr;
+    float *dist = nullptr;
+    unsigned int *ctr = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        hipFree(ids);
+        hipFree(dist);
+        hipFree(ctr);
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+    };
+    if (hipMalloc(&ids, sizeof(uint32_t) * nq * k) != hipSuccess || hipMalloc(&dist, sizeof(float) * nq * k) != hipSuccess ||
+        hipMalloc(&ctr, 256) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(NSG_ENOMEM, "autotune allocation failed");
+    }
+    int lpr0, cpl0;
+    pick_layout(idx->row_chunks, 4, &lpr0, &cpl0);
+    const int lprs[4] = {8, 16, 32, 64};
+    const int hashes[3] = {1024, 2048, 4096};
+    const int wpbs[3] = {1, 2, 4};
+    float bestt = 1e30f;
+    nsg_search_opts bo{};
+    int rc = NSG_OK;
+    for (int li = 0; li < 4 && rc == NSG_OK; ++li) {
+        int c = (idx->row_chunks + lprs[li] - 1) / lprs[li];
+        if (c > 4 || (lprs[li] / 2 >= idx->row_chunks && lprs[li] != lpr0))
+            continue;   // too few lanes for the row, or half of them idle
+        for (int hi = 0; hi < 3 && rc == NSG_OK; ++hi) {
+            if (hashes[hi] < 8 * L && hi < 2) continue;
+            for (int wi = 0; wi < 3 && rc == NSG_OK; ++wi)
+                for (int pers = 0; pers < 2 && rc == NSG_OK; ++pers) {
+                    nsg_search_opts o{};
+                    o.rerank = -1;
+                    o.lanes_per_row = lprs[li];
+                    o.hash_slots = hashes[hi];
+                    o.waves_per_block = wpbs[wi];
+                    o.persistent = pers;
+                    o.counter = ctr;
+                    int r = nsg_search_batched(idx, queries, nq, nullptr, nullptr, k, L, k, ids, dist, &o, stream);
+                    if (r == NSG_EUNSUPPORTED) { clear_error(); continue; }
+                    if (r != NSG_OK) { rc = r; break; }
+                    hipEventRecord(e0, st);
+                    for (int t = 0; t < trials && rc == NSG_OK; ++t)
+                        rc = nsg_search_batched(idx, queries, nq, nullptr, nullptr, k, L, k, ids, dist, &o, stream);
+                    hipEventRecord(e1, st);
+                    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(NSG_EDEVICE, "autotune sync failed"); break; }
+                    float ms = 0.0f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    ms /= (float)trials;
+                    if (ms < bestt) { bestt = ms; bo = o; }
+                }
+        }
+    }
+    cleanup();
+    if (rc != NSG_OK) return rc;
+    bo.counter = nullptr;
+    *best = bo;
+    *best_ms = bestt;
     return NSG_OK;
 }

@@ -476,6 +476,12 @@ int launch_search(const SearchArgs &a) {
         return fail(NSG_EUNSUPPORTED, "search needs %zu bytes of LDS per block", per_wave * wpb);
     int lpr, cpl;
     pick_layout(ix->row_chunks, ix->storage == NSG_E4M3 ? 2 : 4, &lpr, &cpl);
+    if (a.lanes_per_row) {
+        lpr = a.lanes_per_row;
+        cpl = (ix->row_chunks + lpr - 1) / lpr;
+        if (cpl == 3) cpl = 4;
+        if (cpl > 4) return fail(NSG_EINVAL, "lanes_per_row=%d too small for %d chunks per row", lpr, ix->row_chunks);
+    }
     kfn_t fn = nullptr;
     switch (ix->storage) {
     case NSG_F32: fn = pick_kernel<NSG_F32>(lpr, cpl); break;
@@ -490,8 +496,13 @@ int launch_search(const SearchArgs &a) {
     unsigned int *counter = nullptr;
     int64_t blocks;
     if (a.persistent) {
-        NSG_HIP(hipMallocAsync((void **)&counter, sizeof(unsigned int) * 64, a.stream));
-        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, a.stream, counter);
+        if (a.counter) {
+            p.counter = a.counter;
+        } else {
+            NSG_HIP(hipMallocAsync((void **)&counter, sizeof(unsigned int) * 64, a.stream));
+            p.counter = counter;
+        }
+        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, a.stream, p.counter);
         int per_cu = 0;
         NSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 64 * wpb, lds));
         int dev = 0, cus = 0;
@@ -500,7 +511,6 @@ int launch_search(const SearchArgs &a) {
         blocks = a.blocks > 0 ? a.blocks : (int64_t)std::max(1, per_cu) * cus;
         int64_t need = (a.nq + wpb - 1) / wpb;
         if (blocks > need) blocks = need;
-        p.counter = counter;
         // every wave takes its first query from the counter too
     } else {
         blocks = (a.nq + wpb - 1) / wpb;

@@ -145,3 +145,49 @@ def test_pool_output_matches_oracle_pool(tiny_gpu, nsg):
     _, _, _, _, o_pids, o_pd = oracle.search(t["X"], t["graph"], t["nav"], t["Q"][:nq], 10, L, pool_stride=L)
     r = compare(t["X"], t["Q"][:nq], _np(pids).view(np.uint32), _np(pd), o_pids)
     assert r["ok"], r
+
+
+def test_graph_replay_matches_eager(tiny_gpu, nsg):
+    """A batch captured as a HIP graph replays to the eager result every time,
+    with eager work and synchronisation between replays, after refilling the
+    bound query buffer in place."""
+    t = tiny_gpu
+    dev = t["Qd"].device
+    nq = 64
+    k, L = datagen.uneven_kL(nq, 7, k_choices=(1, 10), L_lo=10, L_hi=120)
+    kd = torch.from_numpy(k).to(dev)
+    Ld = torch.from_numpy(L).to(dev)
+    qbuf = t["Qd"][:nq].clone()
+    for persistent in (0, 1):
+        g = nsg.SearchGraph(t["ix"], qbuf, k=kd, L=Ld, L_scalar=120, out_stride=10,
+                            opts=dict(persistent=persistent))
+        for rep in range(4):
+            src = t["Qd"][(rep * 17) % 36:(rep * 17) % 36 + nq]
+            qbuf.copy_(src)
+            ids, dist = g.launch()
+            torch.cuda.synchronize()
+            e_ids, e_dist = nsg.search_batched(t["ix"], src.contiguous(), k=kd, L=Ld, L_scalar=120, out_stride=10)
+            torch.cuda.synchronize()
+            for i in range(nq):
+                assert (ids[i, :k[i]] == e_ids[i, :k[i]]).all() and (dist[i, :k[i]] == e_dist[i, :k[i]]).all()
+        g.close()
+
+
+def test_autotune_returns_working_config(tiny_gpu, nsg):
+    t = tiny_gpu
+    best, ms = nsg.autotune(t["ix"], t["Qd"], 10, 40, trials=2)
+    assert ms > 0 and best["lanes_per_row"] in (8, 16, 32, 64)
+    a = nsg.search(t["ix"], t["Qd"], 10, 40)
+    b = nsg.search_batched(t["ix"], t["Qd"], k_scalar=10, L_scalar=40, opts=best)
+    assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
+
+
+@pytest.mark.parametrize("lpr", [8, 16, 32, 64])
+def test_layouts_agree(tiny_gpu, nsg, lpr):
+    """Every lanes-per-row layout returns the oracle's results (summation
+    order differs only within FP32 rounding)."""
+    t = tiny_gpu
+    ids, dist = nsg.search_batched(t["ix"], t["Qd"], k_scalar=10, L_scalar=50, opts=dict(lanes_per_row=lpr))
+    o_ids, _, _, _ = oracle.search(t["X"], t["graph"], t["nav"], t["Q"], 10, 50)
+    r = compare(t["X"], t["Q"], _np(ids).view(np.uint32), _np(dist), o_ids)
+    assert r["ok"], r
