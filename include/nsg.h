@@ -113,7 +113,7 @@ typedef struct nsg_search_opts {
     int32_t hash_slots;      /* visited-filter slots per query (power of 2); 0: default */
     int32_t blocks;          /* persistent grid size; 0: one wave per resident slot */
     int32_t learned_stop;    /* 1: use the loaded early-stop model (needs L >= 16) */
-    int32_t rerank;          /* -1: default (on for reduced storage), 0 off, 1 on */
+    int32_t rerank;          /* 0: default (on for reduced storage), 1: on, -1: off */
     int64_t *hops;           /* device [nq] expansions per query, or NULL */
     int64_t *ndist;          /* device [nq] distance evaluations per query, or NULL */
     int32_t *L_used;         /* device [nq] pool size after the early stop, or NULL */
@@ -129,6 +129,8 @@ typedef struct nsg_search_opts {
     int32_t lanes_per_row;   /* lanes that gather one row (8, 16, 32, 64); 0: default */
     uint32_t *counter;       /* device scratch word for the persistent work counter (reset by the
                                 call); NULL: allocated per call (not usable under graph capture) */
+    int32_t prefetch;        /* 0: default; 1: on; -1: off.  On: load the neighbour row of the
+                                predicted next expansion while the pool merge runs (results unchanged) */
 } nsg_search_opts;
 
 /*

@@ -51,6 +51,7 @@ class SearchOpts(ctypes.Structure):
         ("nedges", ctypes.c_void_p),
         ("lanes_per_row", ctypes.c_int32),
         ("counter", ctypes.c_void_p),
+        ("prefetch", ctypes.c_int32),
     ]
 
 
@@ -282,7 +283,6 @@ def recall_hits(found, truth, k, stream=None):
 
 def _opts(opts):
     o = SearchOpts()
-    o.rerank = -1
     keep = []
     for key, val in (opts or {}).items():
         if isinstance(val, torch.Tensor):

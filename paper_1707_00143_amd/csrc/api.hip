@@ -122,6 +122,8 @@ static int grid_for(int64_t cnt) {
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65536);
 }
 
+const int kDefaultPrefetch = 0;
+
 int default_hash_bits(int L) {
     int want = L * 12, bits = 10;
     while ((1 << bits) < want && bits < 12) ++bits;
@@ -277,6 +279,7 @@ extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq
     a.L_cap = a.learned ? std::max(L, stop_cap(idx)) : L;
     a.hash_bits = default_hash_bits(a.L_cap);
     a.rerank = idx->storage != NSG_F32;
+    a.prefetch = kDefaultPrefetch;
     a.start_override = NSG_SENT;
     a.self_offset = -1;
     a.stream = (hipStream_t)stream;
@@ -297,7 +300,6 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
         return fail(NSG_EINVAL, "out_stride=%d invalid", out_stride);
     nsg_search_opts o{};
     if (opts) o = *opts;
-    o.rerank = opts ? opts->rerank : -1;
     if (o.hash_slots && (o.hash_slots & (o.hash_slots - 1)))
         return fail(NSG_EINVAL, "hash_slots must be a power of two");
     if (o.hash_slots && (o.hash_slots < 64 || o.hash_slots > 16384))
@@ -330,7 +332,7 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.waves_per_block = o.waves_per_block;
     a.persistent = o.persistent;
     a.blocks = o.blocks;
-    a.rerank = o.rerank < 0 ? (idx->storage != NSG_F32) : (o.rerank != 0);
+    a.rerank = o.rerank == 0 ? (idx->storage != NSG_F32) : (o.rerank > 0);
     a.hops = o.hops;
     a.ndist = o.ndist;
     a.L_used = o.L_used;
@@ -339,6 +341,7 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.nedges = o.nedges;
     a.lanes_per_row = o.lanes_per_row;
     a.counter = o.counter;
+    a.prefetch = o.prefetch == 0 ? kDefaultPrefetch : (o.prefetch > 0);
     a.pool_ids = o.pool_ids;
     a.pool_dist = o.pool_dist;
     a.pool_stride = o.pool_stride;
@@ -444,7 +447,6 @@ extern "C" int nsg_search_graph_create(const nsg_index *idx, const float *querie
     nsg_search_graph *g = new nsg_search_graph();
     nsg_search_opts o{};
     if (opts) o = *opts;
-    else o.rerank = -1;
     if (o.persistent && !o.counter) {
         if (hipMalloc(&g->counter, sizeof(unsigned int) * 64) != hipSuccess) {
             delete g;
@@ -528,7 +530,6 @@ extern "C" int nsg_autotune(const nsg_index *idx, const float *queries, int64_t 
             for (int wi = 0; wi < 3 && rc == NSG_OK; ++wi)
                 for (int pers = 0; pers < 2 && rc == NSG_OK; ++pers) {
                     nsg_search_opts o{};
-                    o.rerank = -1;
                     o.lanes_per_row = lprs[li];
                     o.hash_slots = hashes[hi];
                     o.waves_per_block = wpbs[wi];

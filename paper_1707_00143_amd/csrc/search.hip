@@ -30,6 +30,7 @@ struct KParams {
     float *out_dist;
     int L_cap, L_alloc, hash_bits, lds_per_wave, feat_cap;
     int rerank;
+    int prefetch;
     unsigned int *counter;
     int64_t *hops, *ndist, *nedges;
     int32_t *L_used;
@@ -242,6 +243,8 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
         wave_sync();
         int cursor = 0;
         bool stopped = !learned && !p.features;   // true once the decision hop has passed
+        // neighbour row of the predicted next expansion, loaded during the merge
+        uint32_t pre_v = NSG_SENT, pre_u0 = NSG_SENT, pre_u1 = NSG_SENT;
 
         for (;;) {
             int i = find_unchecked(pool, cursor, size, lane);
@@ -253,10 +256,17 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
             ++hops;
             // neighbour ids (one coalesced row), visited filter, compaction
             const uint32_t *grow = p.graph + (int64_t)v * p.R_pad;
+            uint32_t row0, row1;
+            if (v == pre_v) {
+                row0 = pre_u0;
+                row1 = pre_u1;
+            } else {
+                row0 = lane < p.R ? grow[lane] : NSG_SENT;
+                row1 = lane + 64 < p.R ? grow[lane + 64] : NSG_SENT;
+            }
             int cnt = 0;
             for (int b = 0; b < p.R; b += 64) {
-                int j = b + lane;
-                uint32_t u = j < p.R ? grow[j] : NSG_SENT;
+                uint32_t u = b == 0 ? row0 : row1;
                 ne += __popcll(__ballot(u != NSG_SENT));
                 bool nw = u != NSG_SENT && hash_insert(hash, p.hash_bits, u);
                 uint64_t bm = __ballot(nw);
@@ -277,6 +287,30 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
                         }
                 }
                 vcount += cnt;
+                if (p.prefetch) {
+                    // the next expansion is the better of the best new key that
+                    // enters the pool and the first unchecked entry after i
+                    const uint64_t worst0 = size >= Lcur ? (pool[Lcur - 1] & KEY_MASK) : KEY_NONE;
+                    uint64_t kb = KEY_NONE;
+                    for (int r = lane; r < cnt; r += 64) {
+                        uint64_t kk = mk_key(cdist[r], cid[r]);
+                        kb = kk < kb ? kk : kb;
+                    }
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) {
+                        uint64_t o = shfl_xor64(kb, off);
+                        kb = o < kb ? o : kb;
+                    }
+                    int j = find_unchecked(pool, i + 1, size, lane);
+                    uint64_t kj = j >= 0 ? (pool[j] & KEY_MASK) : KEY_NONE;
+                    uint64_t kn = (kb < worst0 && kb < kj) ? kb : kj;
+                    if (kn != KEY_NONE) {
+                        pre_v = key_id(kn);
+                        const uint32_t *nrow = p.graph + (int64_t)pre_v * p.R_pad;
+                        pre_u0 = lane < p.R ? nrow[lane] : NSG_SENT;
+                        pre_u1 = lane + 64 < p.R ? nrow[lane + 64] : NSG_SENT;
+                    }
+                }
                 // keep candidates below the current L-th key, merge in rounds of 64
                 int first = size;
                 for (int b = 0; b < cnt; b += 64) {
@@ -428,6 +462,7 @@ int launch_search(const SearchArgs &a) {
     p.L_cap = a.L_cap;
     p.hash_bits = a.hash_bits;
     p.rerank = a.rerank;
+    p.prefetch = a.prefetch;
     p.hops = a.hops;
     p.ndist = a.ndist;
     p.nedges = a.nedges;

@@ -43,7 +43,7 @@ def test_reduced_precision_search_parity(nsg, tiny_index, dt):
     pids = torch.empty((len(Q), L), dtype=torch.int32, device=dev)
     pd = torch.empty((len(Q), L), dtype=torch.float32, device=dev)
     ids0, d0 = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L,
-                                  opts=dict(rerank=0, pool_ids=pids, pool_dist=pd, pool_stride=L))
+                                  opts=dict(rerank=-1, pool_ids=pids, pool_dist=pd, pool_stride=L))
     o_ids, o_d, _, _, o_pids, o_pd = oracle.search(Xt, G, nav, Q, k, L, pool_stride=L)
     r = compare(Xt, Q, _np(ids0).view(np.uint32), _np(d0), o_ids)
     assert r["ok"], (dt, {a: b for a, b in r.items() if a != "bad"}, r["bad"][:3])

@@ -191,3 +191,17 @@ def test_layouts_agree(tiny_gpu, nsg, lpr):
     o_ids, _, _, _ = oracle.search(t["X"], t["graph"], t["nav"], t["Q"], 10, 50)
     r = compare(t["X"], t["Q"], _np(ids).view(np.uint32), _np(dist), o_ids)
     assert r["ok"], r
+
+
+def test_prefetch_results_unchanged(tiny_gpu, nsg):
+    """Loading the predicted next row early changes no result or count."""
+    t = tiny_gpu
+    outs = []
+    for pf in (-1, 1):
+        hops = torch.zeros(len(t["Q"]), dtype=torch.int64, device=t["Qd"].device)
+        nd = torch.zeros_like(hops)
+        ids, dist = nsg.search_batched(t["ix"], t["Qd"], k_scalar=10, L_scalar=80,
+                                       opts=dict(prefetch=pf, hops=hops, ndist=nd))
+        outs.append((ids, dist, hops, nd))
+    for a, b in zip(outs[0], outs[1]):
+        assert (a == b).all()
