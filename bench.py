@@ -151,8 +151,9 @@ def main():
     tr = ls.traces(ix16, Tq, ttruth, k=k)
     torch.cuda.synchronize()
     y, reached = ls.labels(tr, k)
+    hist = np.bincount(np.searchsorted(tr.grid, np.exp2(y).round()), minlength=len(tr.grid))
     log(f"traces: {ntr} queries x {len(tr.grid)} pool sizes in {time.time() - t:.1f}s; "
-        f"reached exact top-{k}: {reached.mean():.3f}")
+        f"reached exact top-{k}: {reached.mean():.3f}; label histogram over {tr.grid}: {hist.tolist()}")
     n_fit = int(ntr * 0.9)
     t = time.time()
     P, mean, istd = ls.train(tr.features[:n_fit].contiguous(), y[:n_fit], seed=7, epochs=30,
@@ -243,13 +244,23 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
 
     ms16, wall16 = timed(step16, args.steps, args.warmup)
     r16 = recall(out16[0])
+    out16p = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), device=dev))
+    ms16p = None
+    if f16:
+        def step16p():
+            nsg.search(ix16, Qd, k, int(f16[0]), out_ids=out16p[0], out_dist=out16p[1])
+        ms16p, _ = timed(step16p, args.steps, args.warmup)
+        log(f"plain FP16 (+FP32 re-rank) L={f16[0]}: {ms16p:.3f} ms/step, recall@10 {recall(out16p[0]):.4f}")
     qps32 = nq / (ms32 / 1e3)
     qps16 = nq / (ms16 / 1e3)
     log(f"plain FP32 L={L32}: {ms32:.3f} ms/step, {qps32:,.0f} QPS, recall@10 {r32:.4f}")
     log(f"FP16 + learned stop: {ms16:.3f} ms/step, {qps16:,.0f} QPS, recall@10 {r16:.4f}")
 
     # ---------------- roofline of the dominant kernel (plain FP32 search) ----------------
-    nsg.search_batched(ix32, Qd, k_scalar=k, L_scalar=L32, opts=dict(hops=hops, ndist=ndist, nedges=nedge))
+    # counts with a visited filter large enough never to forget (= the
+    # oracle's exact visited set), so only the method's own bytes are credited
+    nsg.search_batched(ix32, Qd, k_scalar=k, L_scalar=L32,
+                       opts=dict(hops=hops, ndist=ndist, nedges=nedge, hash_slots=16384))
     torch.cuda.synchronize()
     d = X.shape[1]
     H, N, E = hops.sum().item(), ndist.sum().item(), nedge.sum().item()
@@ -307,6 +318,7 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
                         f"NSG R={w.R} l={w.Lb} C={w.C} from exact {w.K}-NN graph; k={k}",
             "plain_fp32": dict(L=L32, qps=round(qps32, 1), ms_per_step=round(ms32, 4), recall10=round(r32, 4)),
             "fp16_learned": dict(qps=round(qps16, 1), recall10=round(r16, 4), **(learned or {})),
+            "plain_fp16_ms_per_step": None if ms16p is None else round(ms16p, 4),
             "plain_fp16_L": f16,
             "speedup_vs_plain_fp32": round(qps16 / qps32, 3),
             "index": dict(nav=nav, repair_edges=rep, aod=round(deg.mean().item(), 2), mod=int(deg.max().item()),

@@ -124,9 +124,11 @@ static int grid_for(int64_t cnt) {
 
 const int kDefaultPrefetch = 0;
 
+// a query visits roughly 25 nodes per pool entry; size the filter to that
+// (it forgets beyond, which only costs recomputation)
 int default_hash_bits(int L) {
-    int want = L * 12, bits = 10;
-    while ((1 << bits) < want && bits < 12) ++bits;
+    int want = L * 24, bits = 10;
+    while ((1 << bits) < want && bits < 13) ++bits;
     return bits;
 }
 
@@ -254,9 +256,7 @@ static int check_search_common(const nsg_index *idx, const float *queries, int64
 
 static int stop_ready(const nsg_index *idx) { return idx->stop.enabled && idx->stop.f32 && idx->stop.grid; }
 
-static int stop_cap(const nsg_index *idx) {
-    return std::max(16, idx->stop.grid_n > 0 ? (int)kMaxL : 16);
-}
+static int stop_cap(const nsg_index *idx) { return std::max(16, idx->stop.grid_max); }
 
 extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
                           uint32_t *out_ids, float *out_dist, void *stream) {
@@ -277,7 +277,7 @@ extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq
     a.out_dist = out_dist;
     a.learned = stop_ready(idx) && L >= 16;
     a.L_cap = a.learned ? std::max(L, stop_cap(idx)) : L;
-    a.hash_bits = default_hash_bits(a.L_cap);
+    a.hash_bits = default_hash_bits(a.learned ? std::max(L, 64) : a.L_cap);
     a.rerank = idx->storage != NSG_F32;
     a.prefetch = kDefaultPrefetch;
     a.start_override = NSG_SENT;
@@ -326,7 +326,8 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.out_dist = out_dist;
     a.learned = o.learned_stop ? 1 : 0;
     a.L_cap = a.learned ? std::max((int)L_scalar, stop_cap(idx)) : L_scalar;
-    int hb = default_hash_bits(a.L_cap);
+    // learned: most queries stop near the fallback L; size the filter for it
+    int hb = default_hash_bits(a.learned ? std::max((int)L_scalar, 64) : a.L_cap);
     if (o.hash_slots) { hb = 0; while ((1 << hb) < o.hash_slots) ++hb; }
     a.hash_bits = hb;
     a.waves_per_block = o.waves_per_block;
@@ -398,6 +399,7 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
     sm.h = h;
     sm.hop = hop;
     sm.grid_n = grid_n;
+    sm.grid_max = (int)grid[grid_n - 1];
     sm.enabled = idx->stop.enabled;
     sm.calib_c = idx->stop.calib_c;
     hipDeviceSynchronize();

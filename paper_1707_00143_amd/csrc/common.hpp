@@ -33,7 +33,7 @@ struct StopModel {
     float *f32 = nullptr;      // device: mean[in], inv_std[in], b1[h], b2[h], b3
     void *w16 = nullptr;       // device FP16: W1T[in][h], W2T[h][h], W3[h]
     float *grid = nullptr;     // device: grid values (ascending)
-    int in = 0, h = 0, hop = 0, grid_n = 0;
+    int in = 0, h = 0, hop = 0, grid_n = 0, grid_max = 16;
     int enabled = 0;
     float calib_c = 1.0f;
 };

@@ -74,13 +74,19 @@ def init_params(n_in, h, seed):
     return np.concatenate(parts).astype(np.float32)
 
 
-def train(features, y, seed=0, epochs=30, batch=1024, lr=1e-3, log=None):
-    """Adam on MSE; returns (params, mean, inv_std) as device tensors."""
+def train(features, y, seed=0, epochs=30, batch=1024, lr=1e-3, min_steps=3000, log=None):
+    """Adam on MSE of standardised targets (at least `min_steps` steps); the
+    target scale and offset are folded into the output layer afterwards.
+    Returns (params, mean, inv_std) as device tensors."""
     dev = features.device
     keep = ~torch.isnan(features).any(1)
     X = features[keep].contiguous()
-    yy = torch.from_numpy(y).to(dev)[keep].contiguous()
+    y = np.asarray(y, np.float32)[keep.cpu().numpy()]
+    mu_y, sd_y = float(y.mean()), float(y.std()) or 1.0
+    yy = torch.from_numpy((y - mu_y) / sd_y).to(dev).contiguous()
     n, n_in = X.shape
+    batch = min(batch, n)
+    epochs = max(epochs, -(-min_steps // max(1, n // batch)))
     mean, istd = column_stats(X)
     Xz = ((X - mean) * istd).contiguous()
     P = torch.from_numpy(init_params(n_in, HIDDEN, seed)).to(dev)
@@ -105,6 +111,9 @@ def train(features, y, seed=0, epochs=30, batch=1024, lr=1e-3, log=None):
                 nb += 1
         if log is not None:
             log(f"  epoch {ep}: loss {tot / max(nb, 1):.4f}")
+    # fold the target standardisation into W3, b3 (the last HIDDEN + 1 values)
+    P[-(HIDDEN + 1):-1] *= sd_y
+    P[-1] = P[-1] * sd_y + mu_y
     return P, mean, istd
 
 

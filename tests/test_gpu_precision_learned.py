@@ -103,16 +103,23 @@ def test_training_reduces_loss(nsg):
     assert mse < 0.25 * float(np.var(y)), (mse, float(np.var(y)))
 
 
-def _random_model(nsg, ix, d, seed):
+def _random_model(nsg, ix, Qd, seed):
+    """Random weights on features z-scored with their own statistics (taken
+    from a feature capture of the plain search), output scaled to spread the
+    picks over the grid."""
     from paper_1707_00143_amd import learned_stop as ls
-    rng = np.random.default_rng(seed)
-    n_in = d + 3
-    P = ls.init_params(n_in, ls.HIDDEN, seed)
-    P[-1] = 5.5          # bias the output towards log2 L ~ 5.5 so picks spread over the grid
-    mean = rng.normal(size=n_in).astype(np.float32) * 10
-    istd = rng.uniform(0.01, 0.1, size=n_in).astype(np.float32)
-    dev = _dev()
-    return torch.from_numpy(P).to(dev), torch.from_numpy(mean).to(dev), torch.from_numpy(istd).to(dev)
+    dev = Qd.device
+    d = Qd.shape[1]
+    feats = torch.empty((Qd.shape[0], d + 3), dtype=torch.float32, device=dev)
+    nsg.search_batched(ix, Qd, k_scalar=10, L_scalar=64, opts=dict(features=feats))
+    mean, istd = nsg.column_stats(feats)
+    P = ls.init_params(d + 3, ls.HIDDEN, seed)
+    Pd = torch.from_numpy(P).to(dev)
+    y = ls.predict(Pd, mean, istd, feats)
+    sd = float(y.std().item()) or 1.0
+    Pd[-(ls.HIDDEN + 1):-1] *= 1.2 / sd          # output spread ~1.2 in log2 L
+    Pd[-1] = (Pd[-1] - float(y.mean().item())) * 1.2 / sd + 5.5
+    return Pd, mean, istd
 
 
 def test_learned_stop_equals_plain_at_chosen_L(nsg, tiny_index):
@@ -127,7 +134,7 @@ def test_learned_stop_equals_plain_at_chosen_L(nsg, tiny_index):
     Qd = torch.from_numpy(Q).to(dev)
     nq, k, L = len(Q), 10, 60
     plain = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L)
-    P, mean, istd = _random_model(nsg, ix, X.shape[1], 5)
+    P, mean, istd = _random_model(nsg, ix, Qd, 5)
     ls.install(ix, P, mean, istd, 1.0)
     Lu = torch.empty(nq, dtype=torch.int32, device=dev)
     feats = torch.empty((nq, X.shape[1] + 3), dtype=torch.float32, device=dev)
