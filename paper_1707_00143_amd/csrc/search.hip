@@ -52,33 +52,52 @@ struct KParams {
     int learned;
 };
 
-// exact FP32 squared distances over the FP32 rows (re-rank), 16 lanes per row
+// exact FP32 squared distances over the FP32 rows (re-rank): 16 lanes per
+// row, 16 rows per round with all their loads issued before the reductions
 __device__ inline void rerank_dist(const KParams &p, const float *q, uint64_t *pool,
                                    int size, int lane) {
     const int g = lane >> 4, li = lane & 15;
     const int rc = p.row_chunks_f32;
-    for (int r0 = 0; r0 < size; r0 += 4) {
-        int r = r0 + g;
-        bool ok = r < size;
-        uint32_t id = ok ? key_id(pool[r]) : 0u;
-        const float4 *row = reinterpret_cast<const float4 *>(p.rows_f32) + (int64_t)id * rc;
-        float acc = 0.0f;
+    for (int r0 = 0; r0 < size; r0 += 16) {
+        uint32_t id[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int r = r0 + 4 * u + g;
+            ok[u] = r < size;
+            id[u] = ok[u] ? key_id(pool[r]) : 0u;
+        }
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int ch = li; ch < rc; ch += 16) {
-            if (!ok) break;
-            float4 x = row[ch];
-            float xs[4] = {x.x, x.y, x.z, x.w};
+            float4 x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                x[u] = ok[u] ? reinterpret_cast<const float4 *>(p.rows_f32)[(int64_t)id[u] * rc + ch]
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            float qc[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 int j = ch * 4 + e;
-                float qj = j < p.d ? q[j] : 0.0f;
-                float t = qj - xs[e];
-                acc = fmaf(t, t, acc);
+                qc[e] = j < p.d ? q[j] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float xs[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float t = qc[e] - xs[e];
+                    acc[u] = fmaf(t, t, acc[u]);
+                }
             }
         }
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off);
         wave_sync();
-        if (li == 0 && ok) pool[r] = mk_key(acc, id);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (li == 0 && ok[u]) pool[r0 + 4 * u + g] = mk_key(acc[u], id[u]);
         wave_sync();
     }
 }
@@ -137,14 +156,16 @@ __device__ inline int stop_predict(const KParams &p, int Lq, int kq, const float
     float a1 = 0.0f;
     if (lane < h) {
         float s = b1[lane];
+#pragma unroll 16
         for (int i = 0; i < in; ++i) s = fmaf((float)W1T[(int64_t)i * h + lane], xbuf[i], s);
         a1 = s > 0.0f ? s : 0.0f;
     }
     float a2 = 0.0f;
     {
         float s = lane < h ? b2[lane] : 0.0f;
+#pragma unroll 16
         for (int j = 0; j < h; ++j) {
-            float aj = __shfl(a1, j);
+            float aj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a1), j));
             if (lane < h) s = fmaf((float)W2T[j * h + lane], aj, s);
         }
         a2 = (lane < h && s > 0.0f) ? s : 0.0f;

@@ -68,10 +68,13 @@ template <> struct Fmt<NSG_E4M3> {
 // ------------------------------------------------------------------------
 // wave primitives
 // ------------------------------------------------------------------------
+// Order LDS accesses between the lanes of one wave.  A wave's LDS operations
+// complete in issue order, so only compiler reordering has to be prevented:
+// a code-motion barrier plus a compiler memory clobber, no memory fence (a
+// fence would also wait for outstanding global loads).
 __device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    asm volatile("" ::: "memory");
 }
 
 __device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
@@ -142,31 +145,50 @@ __device__ inline int lower_bound_pool(const uint64_t *pool, int size, uint64_t 
 // a pool key (a node the visited filter forgot) are dropped, keeping the pool
 // entry and its checked flag.  Returns the new size; *first_ins receives the
 // smallest position written (size if nothing was inserted).
+__device__ inline uint64_t readlane64(uint64_t v, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v & 0xFFFFFFFFu), l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// rank of this lane's key among the keys of the lanes in `mask` (keys distinct)
+__device__ inline int rank_in_mask(uint64_t key, uint64_t mask) {
+    int r = 0;
+    while (mask) {
+        const int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        r += readlane64(key, b) < key;
+    }
+    return r;
+}
+
+// Merge up to 64 candidate keys (one per lane, KEY_NONE = empty) into the
+// sorted pool of `size` entries, keeping the first Lcur.  Candidates equal to
+// a pool key (a node the visited filter forgot) are dropped, keeping the pool
+// entry and its checked flag.  A candidate's new position is its pool lower
+// bound plus its rank among the candidates (ranks by broadcast comparison, no
+// sort); pool entries move right by the number of candidates placed before
+// them.  Returns the new size; *first_ins receives the smallest position
+// written (size if nothing was inserted).
 __device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key,
                           uint32_t *spos, int lane, int *first_ins) {
     *first_ins = size;
-    key = wave_sort64(key, lane);
-    int m = __popcll(__ballot(key != KEY_NONE));
-    if (m == 0) return size;
+    bool valid = key != KEY_NONE;
     int pos = 0;
-    bool dup = false;
-    if (lane < m) {
+    if (valid) {
         pos = lower_bound_pool(pool, size, key);
-        dup = pos < size && (pool[pos] & KEY_MASK) == key;
+        valid = !(pos < size && (pool[pos] & KEY_MASK) == key);
     }
-    uint64_t dm = __ballot(dup);
-    if (dm) {
-        key = dup ? KEY_NONE : key;
-        key = wave_sort64(key, lane);
-        m -= __popcll(dm);
-        if (m == 0) return size;
-        pos = lane < m ? lower_bound_pool(pool, size, key) : 0;
-    }
-    // survivors that would land at or beyond Lcur are dropped by position
-    if (lane < m) spos[lane] = (uint32_t)pos;
+    const uint64_t vm = __ballot(valid);
+    const int m = __popcll(vm);
+    if (m == 0) return size;
+    int rank = 0;
+    if (valid) rank = rank_in_mask(key, vm);
+    // spos[rank] = lower bound: non-decreasing in rank
+    if (valid) spos[rank] = (uint32_t)pos;
     wave_sync();
-    const int p0 = __shfl(pos, 0);
-    if (p0 >= Lcur) { *first_ins = size; return size; }
+    const int p0 = (int)spos[0];
+    if (p0 >= Lcur) return size;
     // shift pool entries [p0, size) right, from the back in chunks of 64
     for (int top = size; top > p0; top -= 64) {
         int i = top - 1 - lane;
@@ -186,8 +208,8 @@ __device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key,
         if (act && np < Lcur) pool[np] = v;
         wave_sync();
     }
-    if (lane < m) {
-        int np = pos + lane;
+    if (valid) {
+        int np = pos + rank;
         if (np < Lcur) pool[np] = key;
     }
     wave_sync();
