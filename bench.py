@@ -44,6 +44,8 @@ def main():
     ap.add_argument("--train", type=int, default=200_000)
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--grid-max", type=int, default=181,
+                    help="largest pool size the learned stop may pick (bounds the slowest query of a batch)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="sift1m_like", choices=["sift1m_like", "deep_uneven"],
                     help="deep_uneven: DEEP-like unit vectors, 100k queries with uneven k and L served in "
@@ -163,15 +165,17 @@ def main():
     yh = ls.predict(P, mean, istd, tr.features[n_fit:].contiguous()).cpu().numpy()
     hold_mse = float(np.mean((yh - y[n_fit:]) ** 2))
     base_mse = float(np.mean((y[n_fit:] - y[:n_fit].mean()) ** 2))
-    cal = ls.calibrate(yh, tr.hits[n_fit:].cpu().numpy(), tr.grid, k, args.target, margin=0.005)
+    grid = [g for g in tr.grid if g <= args.grid_max]
+    cal = ls.calibrate(yh, tr.hits[n_fit:, :len(grid)].cpu().numpy(), grid, k, args.target, margin=0.005)
     log(f"held-out MSE {hold_mse:.4f} (constant predictor {base_mse:.4f}); calibration {cal}")
     c = cal[0] if cal else 4.0
     learned = None
     L_fb = f16[0] if f16 else 512          # fixed-L fallback of the learned mode
     for _ in range(12):
-        ls.install(ix16, P, mean, istd, c)
+        ls.install(ix16, P, mean, istd, c, grid)
         Lu = torch.empty(nq, dtype=torch.int32, device=dev)
-        ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L_fb, opts=dict(learned_stop=1, L_used=Lu))
+        ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L_fb,
+                                    opts=dict(learned_stop=1, L_used=Lu, persistent=1))
         r = recall(ids)
         learned = dict(c=c, recall=r, mean_L=float(Lu.float().mean().item()))
         if r >= args.target:
@@ -181,6 +185,7 @@ def main():
     if cache:
         os.makedirs(args.cache, exist_ok=True)
         np.savez(cache, graph=graph.cpu().numpy(), nav=nav, rep=rep, t_knn=t_knn, t_build=t_build, L32=L32,
+                 grid=np.asarray(grid),
                  L_fb=L_fb, c=c, P=P.cpu().numpy(), mean=mean.cpu().numpy(), istd=istd.cpu().numpy(),
                  f16=np.asarray(f16 if f16 else (0, 0.0)), hold_mse=hold_mse, base_mse=base_mse,
                  sweep=json.dumps(sweep), learned=json.dumps(learned))
@@ -195,7 +200,7 @@ def run_timed(args, z, nsg, ls, torch, dev, w, X, Q, Xd, Qd, ix32, ix16, graph, 
     P = torch.from_numpy(z["P"]).to(dev)
     mean = torch.from_numpy(z["mean"]).to(dev)
     istd = torch.from_numpy(z["istd"]).to(dev)
-    ls.install(ix16, P, mean, istd, float(z["c"]))
+    ls.install(ix16, P, mean, istd, float(z["c"]), [int(g) for g in z["grid"]])
     f16 = tuple(z["f16"].tolist()) if z["f16"][0] else None
     return finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn,
                   t_build, int(z["L32"]), int(z["L_fb"]), f16, json.loads(str(z["learned"])),
@@ -240,7 +245,7 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
 
     def step16():
         nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L_fb, out_ids=out16[0], out_dist=out16[1],
-                           opts=dict(learned_stop=1))
+                           opts=dict(learned_stop=1, persistent=1))
 
     ms16, wall16 = timed(step16, args.steps, args.warmup)
     r16 = recall(out16[0])
@@ -248,7 +253,8 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
     ms16p = None
     if f16:
         def step16p():
-            nsg.search(ix16, Qd, k, int(f16[0]), out_ids=out16p[0], out_dist=out16p[1])
+            nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=int(f16[0]), out_ids=out16p[0], out_dist=out16p[1],
+                               opts=dict(persistent=1))
         ms16p, _ = timed(step16p, args.steps, args.warmup)
         log(f"plain FP16 (+FP32 re-rank) L={f16[0]}: {ms16p:.3f} ms/step, recall@10 {recall(out16p[0]):.4f}")
     qps32 = nq / (ms32 / 1e3)

@@ -123,6 +123,7 @@ static int grid_for(int64_t cnt) {
 }
 
 const int kDefaultPrefetch = 0;
+const int64_t kPersistentMinBatch = 4096;
 
 // a query visits roughly 25 nodes per pool entry; size the filter to that
 // (it forgets beyond, which only costs recomputation)
@@ -280,6 +281,8 @@ extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq
     a.hash_bits = default_hash_bits(a.learned ? std::max(L, 64) : a.L_cap);
     a.rerank = idx->storage != NSG_F32;
     a.prefetch = kDefaultPrefetch;
+    // large batches: persistent grid (work stealing evens out per-query cost)
+    a.persistent = nq >= kPersistentMinBatch;
     a.start_override = NSG_SENT;
     a.self_offset = -1;
     a.stream = (hipStream_t)stream;
