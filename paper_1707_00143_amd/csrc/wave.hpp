@@ -106,18 +106,13 @@ __device__ inline uint64_t wave_sort64(uint64_t key, int lane) {
     return key;
 }
 
-// insert-if-absent; true when u was not in the table (or could not be placed)
+// Visited filter: a direct-mapped table of node ids.  Exchanging u into its
+// slot returns the previous occupant: u itself means u was seen; anything else
+// means it was not (or was evicted by a colliding id, i.e. forgotten, which
+// only costs a recomputation).  It never reports an unseen node as seen.
 __device__ inline bool hash_insert(uint32_t *tab, int bits, uint32_t u) {
-    const uint32_t mask = (1u << bits) - 1u;
-    uint32_t h = (u * 2654435761u) >> (32 - bits);
-#pragma unroll 1
-    for (int t = 0; t < 16; ++t) {
-        uint32_t old = atomicCAS(&tab[h], NSG_SENT, u);
-        if (old == NSG_SENT) return true;
-        if (old == u) return false;
-        h = (h + 1u) & mask;
-    }
-    return true;
+    const uint32_t h = (u * 2654435761u) >> (32 - bits);
+    return atomicExch(&tab[h], u) != u;
 }
 
 // index of the first unchecked pool entry at or after `from`, -1 if none
@@ -140,11 +135,6 @@ __device__ inline int lower_bound_pool(const uint64_t *pool, int size, uint64_t 
     return lo;
 }
 
-// Merge up to 64 candidate keys (one per lane, KEY_NONE = empty) into the
-// sorted pool of `size` entries, keeping the first Lcur.  Candidates equal to
-// a pool key (a node the visited filter forgot) are dropped, keeping the pool
-// entry and its checked flag.  Returns the new size; *first_ins receives the
-// smallest position written (size if nothing was inserted).
 __device__ inline uint64_t readlane64(uint64_t v, int l) {
     uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v & 0xFFFFFFFFu), l);
     uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
@@ -165,56 +155,79 @@ __device__ inline int rank_in_mask(uint64_t key, uint64_t mask) {
 // Merge up to 64 candidate keys (one per lane, KEY_NONE = empty) into the
 // sorted pool of `size` entries, keeping the first Lcur.  Candidates equal to
 // a pool key (a node the visited filter forgot) are dropped, keeping the pool
-// entry and its checked flag.  A candidate's new position is its pool lower
-// bound plus its rank among the candidates (ranks by broadcast comparison, no
-// sort); pool entries move right by the number of candidates placed before
-// them.  Returns the new size; *first_ins receives the smallest position
-// written (size if nothing was inserted).
+// entry and its checked flag.
+//
+// Every position comes from wave-uniform loops over the surviving candidates
+// (usually a handful): for each survivor s, one ballot per 64-entry pool
+// chunk counts the pool keys below it (its lower bound) and detects an equal
+// key; its rank among the survivors is a broadcast comparison.  Pool entry i
+// then moves to i + #{survivors with lower bound <= i}, chunks from the back
+// so nothing is overwritten before it is read.  No dependent LDS chains.
+// Returns the new size; *first_ins receives the smallest position written
+// (size if nothing was inserted).
 __device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key,
                           uint32_t *spos, int lane, int *first_ins) {
+    (void)spos;
     *first_ins = size;
-    bool valid = key != KEY_NONE;
-    int pos = 0;
-    if (valid) {
-        pos = lower_bound_pool(pool, size, key);
-        valid = !(pos < size && (pool[pos] & KEY_MASK) == key);
+    uint64_t sm = __ballot(key != KEY_NONE);
+    if (!sm) return size;
+    const int nch = (size + 63) >> 6;
+    // pass 1: lower bound and duplicate test of every survivor
+    int pos = 0;              // lane s: lower bound of survivor s
+    for (int c = 0; c < nch; ++c) {
+        const int i = (c << 6) + lane;
+        const uint64_t pk = i < size ? (pool[i] & KEY_MASK) : KEY_NONE;
+        uint64_t mm = sm;
+        while (mm) {
+            const int b = __builtin_ctzll(mm);
+            mm &= mm - 1;
+            const uint64_t ks = readlane64(key, b);
+            const int lt = __popcll(__ballot(pk < ks));
+            const bool eq = __ballot(pk == ks) != 0ull;
+            if (lane == b) pos += lt;
+            if (eq) sm &= ~(1ull << b);
+        }
     }
-    const uint64_t vm = __ballot(valid);
-    const int m = __popcll(vm);
+    const int m = __popcll(sm);
     if (m == 0) return size;
+    const bool surv = (sm >> lane) & 1ull;
     int rank = 0;
-    if (valid) rank = rank_in_mask(key, vm);
-    // spos[rank] = lower bound: non-decreasing in rank
-    if (valid) spos[rank] = (uint32_t)pos;
-    wave_sync();
-    const int p0 = (int)spos[0];
+    if (surv) rank = rank_in_mask(key, sm);
+    // smallest lower bound = lower bound of the smallest survivor
+    int p0 = size;
+    {
+        uint64_t mm = sm;
+        while (mm) {
+            const int b = __builtin_ctzll(mm);
+            mm &= mm - 1;
+            p0 = min(p0, __builtin_amdgcn_readlane(pos, b));
+        }
+    }
     if (p0 >= Lcur) return size;
-    // shift pool entries [p0, size) right, from the back in chunks of 64
-    for (int top = size; top > p0; top -= 64) {
-        int i = top - 1 - lane;
-        bool act = i >= p0;
-        uint64_t v = 0;
-        int np = 0;
-        if (act) {
-            v = pool[i];
-            int lo = 0, hi = m;
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if ((int)spos[mid] <= i) lo = mid + 1; else hi = mid;
-            }
-            np = i + lo;
+    // pass 2: move pool entries [p0, size) right, last chunk first
+    for (int c = nch - 1; c >= 0; --c) {
+        const int i = (c << 6) + lane;
+        if ((c << 6) + 63 < p0) break;
+        const bool act = i >= p0 && i < size;
+        const uint64_t v = act ? pool[i] : 0ull;
+        int sh = 0;
+        uint64_t mm = sm;
+        while (mm) {
+            const int b = __builtin_ctzll(mm);
+            mm &= mm - 1;
+            sh += __builtin_amdgcn_readlane(pos, b) <= i;
         }
         wave_sync();
-        if (act && np < Lcur) pool[np] = v;
+        if (act && i + sh < Lcur) pool[i + sh] = v;
         wave_sync();
     }
-    if (valid) {
-        int np = pos + rank;
+    if (surv) {
+        const int np = pos + rank;
         if (np < Lcur) pool[np] = key;
     }
     wave_sync();
     *first_ins = p0;
-    int ns = size + m;
+    const int ns = size + m;
     return ns < Lcur ? ns : Lcur;
 }
 
