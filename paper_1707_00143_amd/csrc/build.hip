@@ -25,6 +25,7 @@ namespace nsg {
 struct SelParams {
     const uint4 *rows;       // FP32 rows, stride row_chunks
     int row_chunks;
+    uint32_t n_rows;
     const uint32_t *vis_ids;
     const float *vis_dist;
     const int32_t *vis_cnt;
@@ -63,7 +64,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelParams p) {
             }
         }
         int fi;
-        size = merge_pool(pool, size, p.C, key, spos, lane, &fi);
+        size = merge_pool(pool, size, p.C, key, lane, &fi, true);
     }
     // MRNG selection over the sorted candidates
     constexpr int EPC = 4;
@@ -72,7 +73,8 @@ __global__ void __launch_bounds__(256) select_kernel(SelParams p) {
     int s = 0;
     for (int t = 0; t < size && s < p.m; ++t) {
         const uint64_t pk = pool[t];
-        const uint32_t pid = key_id(pk);
+        uint32_t pid = key_id(pk);
+        pid = pid < p.n_rows ? pid : 0u;
         const float dvp = key_dist(pk);
         bool conflict = false;
         if (s > 0) {
@@ -86,7 +88,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelParams p) {
 #pragma unroll
                 for (int e = 0; e < EPC; ++e) sc[c][e] = 0.0f;
             }
-            gather_dist<NSG_F32, LPR, CPL>(p.rows, p.row_chunks, qv, sc, sel, cdist, s, lane);
+            gather_dist<NSG_F32, LPR, CPL>(p.rows, p.row_chunks, p.n_rows, qv, sc, sel, cdist, s, lane);
             wave_sync();
             bool c0 = lane < s && cdist[lane] < dvp;
             bool c1 = lane + 64 < s && cdist[lane + 64] < dvp;
@@ -229,6 +231,7 @@ extern "C" int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t
     SelParams sp{};
     sp.rows = reinterpret_cast<const uint4 *>(kix->base_f32);
     sp.row_chunks = kix->row_chunks_f32;
+    sp.n_rows = (uint32_t)n;
     sp.vis_ids = vid;
     sp.vis_dist = vdist;
     sp.vis_cnt = vcnt;

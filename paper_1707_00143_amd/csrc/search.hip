@@ -20,6 +20,7 @@ struct KParams {
     const float *rows_f32;       // FP32 rows for re-ranking, stride row_chunks_f32 * 4
     const uint32_t *graph;
     int R, R_pad;
+    uint32_t n_rows;
     int d, row_chunks, row_chunks_f32;
     uint32_t start;
     const float *queries;
@@ -66,6 +67,7 @@ __device__ inline void rerank_dist(const KParams &p, const float *q, uint64_t *p
             int r = r0 + 4 * u + g;
             ok[u] = r < size;
             id[u] = ok[u] ? key_id(pool[r]) : 0u;
+            id[u] = id[u] < p.n_rows ? id[u] : 0u;
         }
         float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int ch = li; ch < rc; ch += 16) {
@@ -251,7 +253,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
         // pool <- {start}
         if (lane == 0) { cid[0] = start; hash_insert(hash, p.hash_bits, start); }
         wave_sync();
-        gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, qv, sc, cid, cdist, 1, lane);
+        gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, p.n_rows, qv, sc, cid, cdist, 1, lane);
         wave_sync();
         nd = 1;
         if (rec && lane == 0 && vcount < p.vis_cap) {
@@ -273,7 +275,8 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
             uint64_t pe = pool[i];
             wave_sync();
             if (lane == 0) pool[i] = pe | CHECKED_BIT;
-            const uint32_t v = key_id(pe);
+            uint32_t v = key_id(pe);
+            v = v < p.n_rows ? v : 0u;
             ++hops;
             // neighbour ids (one coalesced row), visited filter, compaction
             const uint32_t *grow = p.graph + (int64_t)v * p.R_pad;
@@ -297,7 +300,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
             }
             wave_sync();
             if (cnt > 0) {
-                gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, qv, sc, cid, cdist, cnt, lane);
+                gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, p.n_rows, qv, sc, cid, cdist, cnt, lane);
                 wave_sync();
                 nd += cnt;
                 if (rec) {
@@ -343,7 +346,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
                         if (kk < worst) key = kk;
                     }
                     int fi;
-                    size = merge_pool(pool, size, Lcur, key, spos, lane, &fi);
+                    size = merge_pool(pool, size, Lcur, key, lane, &fi, true);
                     first = fi < first ? fi : first;
                 }
                 cursor = (i + 1) < first ? (i + 1) : first;
@@ -385,7 +388,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
             }
             wave_sync();
             if (cnt > 0) {
-                gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, qv, sc, cid, cdist, cnt, lane);
+                gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, p.n_rows, qv, sc, cid, cdist, cnt, lane);
                 wave_sync();
                 if (rec)
                     for (int r = lane; r < cnt; r += 64)
@@ -468,6 +471,7 @@ int launch_search(const SearchArgs &a) {
     p.R = a.graph_override ? a.R_override : ix->R;
     p.R_pad = a.graph_override ? a.Rpad_override : ix->R_pad;
     p.d = ix->d;
+    p.n_rows = (uint32_t)ix->n;
     p.row_chunks = ix->row_chunks;
     p.row_chunks_f32 = ix->row_chunks_f32;
     p.start = a.start_override != NSG_SENT ? a.start_override : ix->nav;

@@ -163,14 +163,26 @@ __device__ inline int rank_in_mask(uint64_t key, uint64_t mask) {
 // key; its rank among the survivors is a broadcast comparison.  Pool entry i
 // then moves to i + #{survivors with lower bound <= i}, chunks from the back
 // so nothing is overwritten before it is read.  No dependent LDS chains.
+// When `may_repeat` is set the batch itself may hold one key more than once
+// (a node recorded twice); later copies are dropped first, so that ranks are
+// distinct and every position in [p0, p0 + m) is written.
 // Returns the new size; *first_ins receives the smallest position written
 // (size if nothing was inserted).
 __device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key,
-                          uint32_t *spos, int lane, int *first_ins) {
-    (void)spos;
+                          int lane, int *first_ins, bool may_repeat = false) {
     *first_ins = size;
     uint64_t sm = __ballot(key != KEY_NONE);
     if (!sm) return size;
+    if (may_repeat) {
+        bool again = false;
+        uint64_t mm = sm;
+        while (mm) {
+            const int b = __builtin_ctzll(mm);
+            mm &= mm - 1;
+            again |= lane > b && readlane64(key, b) == key;
+        }
+        sm = __ballot(key != KEY_NONE && !again);
+    }
     const int nch = (size + 63) >> 6;
     // pass 1: lower bound and duplicate test of every survivor
     int pos = 0;              // lane s: lower bound of survivor s
@@ -233,7 +245,8 @@ __device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key,
 
 // squared distances of q to the rows cid[0..cnt) (search format) -> cdist
 template <int DT, int LPR, int CPL>
-__device__ inline void gather_dist(const uint4 *rows, int row_chunks, const float (&qv)[CPL][Fmt<DT>::EPC],
+__device__ inline void gather_dist(const uint4 *rows, int row_chunks, uint32_t n_rows,
+                                   const float (&qv)[CPL][Fmt<DT>::EPC],
                                    const float (&sc)[CPL][Fmt<DT>::EPC],
                                    const uint32_t *cid, float *cdist, int cnt, int lane) {
     constexpr int EPC = Fmt<DT>::EPC;
@@ -247,6 +260,7 @@ __device__ inline void gather_dist(const uint4 *rows, int row_chunks, const floa
             int r = r0 + u * RPP + g;
             bool ok = r < cnt;
             uint32_t id = ok ? cid[r] : 0u;
+            id = id < n_rows ? id : 0u;     // never index past the base
             const uint4 *row = rows + (int64_t)id * row_chunks;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
