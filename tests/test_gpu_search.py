@@ -205,3 +205,24 @@ def test_prefetch_results_unchanged(tiny_gpu, nsg):
         outs.append((ids, dist, hops, nd))
     for a, b in zip(outs[0], outs[1]):
         assert (a == b).all()
+
+
+def test_repeated_ids_and_tiny_filter_regression(tiny_gpu, nsg):
+    """Rows that repeat ids, searched with a 64-slot visited filter: nodes are
+    recomputed and offered twice in one merge batch; results still equal the
+    oracle's (regression: a repeated key once left an unwritten pool slot)."""
+    t = tiny_gpu
+    G = t["graph"].copy()
+    rng = np.random.default_rng(11)
+    for v in range(G.shape[0]):
+        row = G[v][G[v] != 0xFFFFFFFF]
+        if len(row) >= 4:
+            j = rng.integers(1, len(row))
+            G[v, j] = row[0]                      # repeat the first id inside the row
+    dev = t["Qd"].device
+    ix = nsg.load_index(t["Xd"], torch.from_numpy(G.view(np.int32)).to(dev), t["nav"])
+    ids, dist = nsg.search_batched(ix, t["Qd"], k_scalar=10, L_scalar=60, opts=dict(hash_slots=64))
+    o_ids, _, _, _ = oracle.search(t["X"], G, t["nav"], t["Q"], 10, 60)
+    r = compare(t["X"], t["Q"], _np(ids).view(np.uint32), _np(dist), o_ids)
+    assert r["ok"], r
+    ix.close()
