@@ -1,0 +1,6 @@
+// Search kernels for bf16 rows (instantiations of search_impl.hpp).
+#include "search_impl.hpp"
+
+namespace nsg {
+kfn_t pick_search_kernel_bf16(int lpr, int cpl, bool full) { return pick_kernel_t<NSG_BF16>(lpr, cpl, full); }
+}  // namespace nsg
