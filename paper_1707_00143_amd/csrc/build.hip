@@ -44,8 +44,8 @@ __global__ void __launch_bounds__(256) select_kernel(SelParams p) {
     if (b >= p.nb) return;
     unsigned char *wb = smem + (size_t)wave * p.lds_per_wave;
     uint64_t *pool = reinterpret_cast<uint64_t *>(wb);
-    uint32_t *spos = reinterpret_cast<uint32_t *>(pool + p.C_alloc);
-    uint32_t *sel = spos + 64;
+    uint64_t *sbuf = pool + p.C_alloc;   // 16 staged keys (+16 spare)
+    uint32_t *sel = reinterpret_cast<uint32_t *>(sbuf + 32);
     float *cdist = reinterpret_cast<float *>(sel + kMaxR);
     const uint32_t v = (uint32_t)(p.node0 + b);
     const uint32_t *vid = p.vis_ids + b * (int64_t)p.vis_cap;
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelParams p) {
             }
         }
         int fi;
-        size = merge_pool(pool, size, p.C, key, lane, &fi, true);
+        size = merge_pool(pool, size, p.C, key, sbuf, lane, &fi);
     }
     // MRNG selection over the sorted candidates
     constexpr int EPC = 4;
@@ -240,7 +240,7 @@ extern "C" int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t
     sp.C_alloc = C_alloc;
     sp.m = R;
     sp.graph = graph_out;
-    sp.lds_per_wave = (int)(((size_t)C_alloc * 8 + 64 * 4 + kMaxR * 4 + kMaxR * 4 + 15) & ~(size_t)15);
+    sp.lds_per_wave = (int)(((size_t)C_alloc * 8 + 32 * 8 + kMaxR * 4 + kMaxR * 4 + 15) & ~(size_t)15);
     const int swpb = 4;
     int64_t overflow = 0;
     std::vector<int32_t> hcnt((size_t)B);

@@ -91,7 +91,7 @@ int launch_search(const SearchArgs &a) {
     int L_alloc = 1;
     while (L_alloc < a.L_cap) L_alloc <<= 1;
     p.L_alloc = L_alloc;
-    size_t per_wave = (size_t)L_alloc * 8 + ((size_t)4 << a.hash_bits) + kMaxR * 8 + 64 * 4 +
+    size_t per_wave = (size_t)L_alloc * 8 + ((size_t)4 << a.hash_bits) + kMaxR * 8 + 32 * 8 +
                       (size_t)p.feat_cap * 4;
     per_wave = (per_wave + 15) & ~(size_t)15;
     p.lds_per_wave = (int)per_wave;

@@ -198,8 +198,8 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
     uint32_t *hash = reinterpret_cast<uint32_t *>(pool + p.L_alloc);
     uint32_t *cid = hash + (1 << p.hash_bits);
     float *cdist = reinterpret_cast<float *>(cid + kMaxR);
-    uint32_t *spos = reinterpret_cast<uint32_t *>(cdist + kMaxR);
-    float *xbuf = reinterpret_cast<float *>(spos + 64);
+    uint64_t *sbuf = reinterpret_cast<uint64_t *>(cdist + kMaxR);   // 16 staged keys (+16 spare)
+    float *xbuf = reinterpret_cast<float *>(sbuf + 32);
     const int H = 1 << p.hash_bits;
 
     int64_t qi;
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
                         if (kk < worst) key = kk;
                     }
                     int fi;
-                    size = merge_pool(pool, size, Lcur, key, lane, &fi, true);
+                    size = merge_pool(pool, size, Lcur, key, sbuf, lane, &fi);
                     first = fi < first ? fi : first;
                 }
                 cursor = (i + 1) < first ? (i + 1) : first;

@@ -141,106 +141,112 @@ __device__ inline uint64_t readlane64(uint64_t v, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// rank of this lane's key among the keys of the lanes in `mask` (keys distinct)
-__device__ inline int rank_in_mask(uint64_t key, uint64_t mask) {
-    int r = 0;
-    while (mask) {
-        const int b = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        r += readlane64(key, b) < key;
-    }
-    return r;
+__device__ inline uint64_t readfirstlane64(uint64_t v) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v & 0xFFFFFFFFu));
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// Merge up to 64 candidate keys (one per lane, KEY_NONE = empty) into the
-// sorted pool of `size` entries, keeping the first Lcur.  Candidates equal to
-// a pool key (a node the visited filter forgot) are dropped, keeping the pool
-// entry and its checked flag.
+// Merge the M keys staged in sbuf[0..M) (KEY_NONE = empty) into the sorted
+// pool of `size` entries, keeping the first Lcur.
 //
-// Every position comes from wave-uniform loops over the surviving candidates
-// (usually a handful): for each survivor s, one ballot per 64-entry pool
-// chunk counts the pool keys below it (its lower bound) and detects an equal
-// key; its rank among the survivors is a broadcast comparison.  Pool entry i
-// then moves to i + #{survivors with lower bound <= i}, chunks from the back
-// so nothing is overwritten before it is read.  No dependent LDS chains.
-// When `may_repeat` is set the batch itself may hold one key more than once
-// (a node recorded twice); later copies are dropped first, so that ranks are
-// distinct and every position in [p0, p0 + m) is written.
-// Returns the new size; *first_ins receives the smallest position written
-// (size if nothing was inserted).
-__device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key,
-                          int lane, int *first_ins, bool may_repeat = false) {
-    *first_ins = size;
-    uint64_t sm = __ballot(key != KEY_NONE);
-    if (!sm) return size;
-    if (may_repeat) {
-        bool again = false;
-        uint64_t mm = sm;
-        while (mm) {
-            const int b = __builtin_ctzll(mm);
-            mm &= mm - 1;
-            again |= lane > b && readlane64(key, b) == key;
-        }
-        sm = __ballot(key != KEY_NONE && !again);
-    }
+// The staged keys are read back as wave-uniform values, so every step is a
+// fixed, unrolled set of independent compares and ballots (no loop whose trip
+// count depends on the data).  A staged key is dropped if an earlier staged
+// key equals it (a node recorded twice) or if the pool holds it (a node the
+// visited filter forgot; the pool entry keeps its checked flag).  For each
+// kept key j: lb_j = #pool keys below it, rank_j = #kept keys below it; pool
+// entry i moves to i + #{kept keys below it} (chunks last first, so nothing is
+// overwritten before it is read) and key j goes to lb_j + rank_j.  Positions
+// at or beyond Lcur are not written.
+template <int M>
+__device__ int merge_staged(uint64_t *pool, int size, int Lcur, const uint64_t *sbuf, int lane,
+                            int *first_ins) {
+    uint64_t bk[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) bk[j] = readfirstlane64(sbuf[j]);
+    const uint64_t mine = lane < M ? sbuf[lane] : KEY_NONE;
+    bool dup = false;
+#pragma unroll
+    for (int j = 0; j < M - 1; ++j) dup |= (j < lane) && bk[j] == mine;
+    uint32_t keep = (uint32_t)__ballot(mine != KEY_NONE && !dup);
     const int nch = (size + 63) >> 6;
-    // pass 1: lower bound and duplicate test of every survivor
-    int pos = 0;              // lane s: lower bound of survivor s
+    int lb[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) lb[j] = 0;
     for (int c = 0; c < nch; ++c) {
         const int i = (c << 6) + lane;
         const uint64_t pk = i < size ? (pool[i] & KEY_MASK) : KEY_NONE;
-        uint64_t mm = sm;
-        while (mm) {
-            const int b = __builtin_ctzll(mm);
-            mm &= mm - 1;
-            const uint64_t ks = readlane64(key, b);
-            const int lt = __popcll(__ballot(pk < ks));
-            const bool eq = __ballot(pk == ks) != 0ull;
-            if (lane == b) pos += lt;
-            if (eq) sm &= ~(1ull << b);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            lb[j] += __popcll(__ballot(pk < bk[j]));
+            if (__ballot(pk == bk[j])) keep &= ~(1u << j);
         }
     }
-    const int m = __popcll(sm);
-    if (m == 0) return size;
-    const bool surv = (sm >> lane) & 1ull;
-    int rank = 0;
-    if (surv) rank = rank_in_mask(key, sm);
-    // smallest lower bound = lower bound of the smallest survivor
+    if (!keep) return size;
     int p0 = size;
-    {
-        uint64_t mm = sm;
-        while (mm) {
-            const int b = __builtin_ctzll(mm);
-            mm &= mm - 1;
-            p0 = min(p0, __builtin_amdgcn_readlane(pos, b));
-        }
-    }
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        if ((keep >> j) & 1u) p0 = lb[j] < p0 ? lb[j] : p0;
     if (p0 >= Lcur) return size;
-    // pass 2: move pool entries [p0, size) right, last chunk first
-    for (int c = nch - 1; c >= 0; --c) {
+    // pool entries [p0, size) move right, last chunk first
+    for (int c = nch - 1; c >= 0 && (c << 6) + 63 >= p0; --c) {
         const int i = (c << 6) + lane;
-        if ((c << 6) + 63 < p0) break;
         const bool act = i >= p0 && i < size;
         const uint64_t v = act ? pool[i] : 0ull;
+        const uint64_t vk = v & KEY_MASK;
         int sh = 0;
-        uint64_t mm = sm;
-        while (mm) {
-            const int b = __builtin_ctzll(mm);
-            mm &= mm - 1;
-            sh += __builtin_amdgcn_readlane(pos, b) <= i;
-        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) sh += (((keep >> j) & 1u) && bk[j] < vk) ? 1 : 0;
         wave_sync();
         if (act && i + sh < Lcur) pool[i + sh] = v;
         wave_sync();
     }
-    if (surv) {
-        const int np = pos + rank;
-        if (np < Lcur) pool[np] = key;
+    // kept staged keys: lane j places key j
+    int pos = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        pos += (((keep >> j) & 1u) && bk[j] < mine) ? 1 : 0;
+        pos += lane == j ? lb[j] : 0;
     }
+    if (lane < M && ((keep >> lane) & 1u) && pos < Lcur) pool[pos] = mine;
     wave_sync();
     *first_ins = p0;
-    const int ns = size + m;
+    const int ns = size + __popc(keep);
     return ns < Lcur ? ns : Lcur;
+}
+
+// Merge up to 64 candidate keys (one per lane, KEY_NONE = empty) into the
+// sorted pool: the non-empty keys are staged, in lane order, in groups of at
+// most 16 in sbuf (16 entries of LDS owned by the caller) and merged group by
+// group.  Returns the new size; *first_ins receives the smallest position
+// written (size if nothing was inserted).
+__device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key, uint64_t *sbuf,
+                          int lane, int *first_ins) {
+    *first_ins = size;
+    const bool surv = key != KEY_NONE;
+    const uint64_t sm = __ballot(surv);
+    if (!sm) return size;
+    const int m = __popcll(sm);
+    const int idx = __popcll(sm & ((1ull << lane) - 1ull));
+    for (int g = 0; g * 16 < m; ++g) {
+        const int mg = m - g * 16 < 16 ? m - g * 16 : 16;
+        const int M = mg <= 4 ? 4 : (mg <= 8 ? 8 : 16);
+        if (lane < M) sbuf[lane] = KEY_NONE;
+        wave_sync();
+        if (surv && (idx >> 4) == g) sbuf[idx & 15] = key;
+        wave_sync();
+        int fi = size;
+        if (M == 4)
+            size = merge_staged<4>(pool, size, Lcur, sbuf, lane, &fi);
+        else if (M == 8)
+            size = merge_staged<8>(pool, size, Lcur, sbuf, lane, &fi);
+        else
+            size = merge_staged<16>(pool, size, Lcur, sbuf, lane, &fi);
+        *first_ins = fi < *first_ins ? fi : *first_ins;
+        wave_sync();
+    }
+    return size;
 }
 
 // squared distances of q to the rows cid[0..cnt) (search format) -> cdist
