@@ -129,8 +129,6 @@ typedef struct nsg_search_opts {
     int32_t lanes_per_row;   /* lanes that gather one row (8, 16, 32, 64); 0: default */
     uint32_t *counter;       /* device scratch word for the persistent work counter (reset by the
                                 call); NULL: allocated per call (not usable under graph capture) */
-    int32_t prefetch;        /* 0: default; 1: on; -1: off.  On: load the neighbour row of the
-                                predicted next expansion while the pool merge runs (results unchanged) */
 } nsg_search_opts;
 
 /*

@@ -51,7 +51,6 @@ class SearchOpts(ctypes.Structure):
         ("nedges", ctypes.c_void_p),
         ("lanes_per_row", ctypes.c_int32),
         ("counter", ctypes.c_void_p),
-        ("prefetch", ctypes.c_int32),
     ]
 
 

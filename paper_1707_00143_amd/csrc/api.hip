@@ -122,13 +122,12 @@ static int grid_for(int64_t cnt) {
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65536);
 }
 
-const int kDefaultPrefetch = 0;
 const int64_t kPersistentMinBatch = 4096;
 
 // a query visits roughly 25 nodes per pool entry; size the filter to that
 // (it forgets beyond, which only costs recomputation)
 int default_hash_bits(int L) {
-    int want = L * 24, bits = 10;
+    int want = L * 12, bits = 10;
     while ((1 << bits) < want && bits < 13) ++bits;
     return bits;
 }
@@ -280,7 +279,6 @@ extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq
     a.L_cap = a.learned ? std::max(L, stop_cap(idx)) : L;
     a.hash_bits = default_hash_bits(a.learned ? std::max(L, 64) : a.L_cap);
     a.rerank = idx->storage != NSG_F32;
-    a.prefetch = kDefaultPrefetch;
     // large batches: persistent grid (work stealing evens out per-query cost)
     a.persistent = nq >= kPersistentMinBatch;
     a.start_override = NSG_SENT;
@@ -345,7 +343,6 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.nedges = o.nedges;
     a.lanes_per_row = o.lanes_per_row;
     a.counter = o.counter;
-    a.prefetch = o.prefetch == 0 ? kDefaultPrefetch : (o.prefetch > 0);
     a.pool_ids = o.pool_ids;
     a.pool_dist = o.pool_dist;
     a.pool_stride = o.pool_stride;

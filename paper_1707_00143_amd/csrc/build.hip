@@ -39,7 +39,8 @@ struct SelParams {
 template <int LPR, int CPL>
 __global__ void __launch_bounds__(256) select_kernel(SelParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wpb = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t b = (int64_t)blockIdx.x * wpb + wave;
     if (b >= p.nb) return;
     unsigned char *wb = smem + (size_t)wave * p.lds_per_wave;

@@ -84,7 +84,6 @@ struct SearchArgs {
     int64_t *nedges;          // valid neighbour entries read, summed over expansions
     int32_t feature_hop;      // decision / trace hop (0: 16)
     int32_t lanes_per_row;    // 0: default layout
-    int32_t prefetch;         // load the predicted next row during the merge
     unsigned int *counter;    // persistent work counter (NULL: allocated per call)
     int32_t *L_used;
     float *features;

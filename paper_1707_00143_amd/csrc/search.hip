@@ -22,10 +22,18 @@ void pick_layout(int chunks, int max_cpl, int *lpr, int *cpl) {
 
 __global__ void reset_counter_kernel(unsigned int *c) { if (threadIdx.x == 0) c[0] = 0u; }
 
-kfn_t pick_search_kernel_f32(int lpr, int cpl, bool full);
-kfn_t pick_search_kernel_bf16(int lpr, int cpl, bool full);
-kfn_t pick_search_kernel_f16(int lpr, int cpl, bool full);
-kfn_t pick_search_kernel_e4m3(int lpr, int cpl, bool full);
+kfn_t pick_search_kernel_f32(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_f32_learn(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_f32_full(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_bf16(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_bf16_learn(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_bf16_full(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_f16(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_f16_learn(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_f16_full(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_e4m3(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_e4m3_learn(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_e4m3_full(int lpr, int cpl, int nch);
 
 int launch_search(const SearchArgs &a) {
     const nsg_index *ix = a.idx;
@@ -55,7 +63,6 @@ int launch_search(const SearchArgs &a) {
     p.L_cap = a.L_cap;
     p.hash_bits = a.hash_bits;
     p.rerank = a.rerank;
-    p.prefetch = a.prefetch;
     p.hops = a.hops;
     p.ndist = a.ndist;
     p.nedges = a.nedges;
@@ -91,8 +98,8 @@ int launch_search(const SearchArgs &a) {
     int L_alloc = 1;
     while (L_alloc < a.L_cap) L_alloc <<= 1;
     p.L_alloc = L_alloc;
-    size_t per_wave = (size_t)L_alloc * 8 + ((size_t)4 << a.hash_bits) + kMaxR * 8 + 32 * 8 +
-                      (size_t)p.feat_cap * 4;
+    // pool, visited filter, candidate ids and distances, features
+    size_t per_wave = (size_t)L_alloc * 8 + ((size_t)4 << a.hash_bits) + kMaxR * 8 + (size_t)p.feat_cap * 4;
     per_wave = (per_wave + 15) & ~(size_t)15;
     p.lds_per_wave = (int)per_wave;
     int wpb = a.waves_per_block;
@@ -110,14 +117,28 @@ int launch_search(const SearchArgs &a) {
         if (cpl == 3) cpl = 4;
         if (cpl > 4) return fail(NSG_EINVAL, "lanes_per_row=%d too small for %d chunks per row", lpr, ix->row_chunks);
     }
-    const bool full = a.learned || a.features || a.vis_ids || a.pool_ids || a.prefetch || a.hops || a.ndist ||
-                      a.nedges || a.L_used || a.self_offset >= 0;
+    const bool full = a.features || a.vis_ids || a.pool_ids || a.hops || a.ndist || a.nedges ||
+                      a.self_offset >= 0;
+    const int mode = full ? 2 : (a.learned || a.L_used) ? 1 : 0;
+    const int nch = L_alloc <= 128 ? 2 : L_alloc <= 256 ? 4 : 8;   // pool registers per lane: 2 * nch
     kfn_t fn = nullptr;
     switch (ix->storage) {
-    case NSG_F32: fn = pick_search_kernel_f32(lpr, cpl, full); break;
-    case NSG_BF16: fn = pick_search_kernel_bf16(lpr, cpl, full); break;
-    case NSG_F16: fn = pick_search_kernel_f16(lpr, cpl, full); break;
-    case NSG_E4M3: fn = pick_search_kernel_e4m3(lpr, cpl, full); break;
+    case NSG_F32: fn = mode == 2 ? pick_search_kernel_f32_full(lpr, cpl, nch)
+                       : mode == 1 ? pick_search_kernel_f32_learn(lpr, cpl, nch)
+                                   : pick_search_kernel_f32(lpr, cpl, nch);
+        break;
+    case NSG_BF16: fn = mode == 2 ? pick_search_kernel_bf16_full(lpr, cpl, nch)
+                       : mode == 1 ? pick_search_kernel_bf16_learn(lpr, cpl, nch)
+                                   : pick_search_kernel_bf16(lpr, cpl, nch);
+        break;
+    case NSG_F16: fn = mode == 2 ? pick_search_kernel_f16_full(lpr, cpl, nch)
+                       : mode == 1 ? pick_search_kernel_f16_learn(lpr, cpl, nch)
+                                   : pick_search_kernel_f16(lpr, cpl, nch);
+        break;
+    case NSG_E4M3: fn = mode == 2 ? pick_search_kernel_e4m3_full(lpr, cpl, nch)
+                       : mode == 1 ? pick_search_kernel_e4m3_learn(lpr, cpl, nch)
+                                   : pick_search_kernel_e4m3(lpr, cpl, nch);
+        break;
     }
     if (!fn) return fail(NSG_EUNSUPPORTED, "no search kernel for %d chunks per row", ix->row_chunks);
     size_t lds = per_wave * wpb;

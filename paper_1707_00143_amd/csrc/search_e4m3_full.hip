@@ -1,0 +1,7 @@
+// Search kernels for e4m3 rows with every option compiled in (learned stop,
+// feature capture, visit recording, pool output, statistics).
+#include "search_impl.hpp"
+
+namespace nsg {
+kfn_t pick_search_kernel_e4m3_full(int lpr, int cpl, int nch) { return pick_kernel_t<NSG_E4M3, 2>(lpr, cpl, nch); }
+}  // namespace nsg

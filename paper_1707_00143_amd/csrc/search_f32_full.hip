@@ -1,0 +1,7 @@
+// Search kernels for f32 rows with every option compiled in (learned stop,
+// feature capture, visit recording, pool output, statistics).
+#include "search_impl.hpp"
+
+namespace nsg {
+kfn_t pick_search_kernel_f32_full(int lpr, int cpl, int nch) { return pick_kernel_t<NSG_F32, 2>(lpr, cpl, nch); }
+}  // namespace nsg

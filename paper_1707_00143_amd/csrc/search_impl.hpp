@@ -22,7 +22,6 @@ struct KParams {
     float *out_dist;
     int L_cap, L_alloc, hash_bits, lds_per_wave, feat_cap;
     int rerank;
-    int prefetch;
     unsigned int *counter;
     int64_t *hops, *ndist, *nedges;
     int32_t *L_used;
@@ -84,9 +83,7 @@ __device__ inline void rerank_dist(const KParams &p, const float *q, uint64_t *p
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int off = 8; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off);
+        for (int u = 0; u < 4; ++u) acc[u] = group_sum<16>(acc[u]);
         wave_sync();
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -118,20 +115,21 @@ __device__ inline void lds_sort(uint64_t *a, int n, int cap, int lane) {
 
 // early-stop features after the decision expansion: the query, the best pool
 // distance, the ratio of the 1st to the 10th pool distance, the hop count.
-// Written raw to p.features (if given) and z-scored into xbuf (if learned).
-__device__ inline void stop_features(const KParams &p, const float *q, const uint64_t *pool,
-                                     int size, int64_t hops, float *xbuf, int lane, int64_t qi) {
+// Written raw to p.features (if given and WF) and z-scored into xbuf (if learned).
+template <bool WF>
+__device__ inline void stop_features(const KParams &p, const float *q, float d0, float d9,
+                                     int64_t hops, float *xbuf, int lane, int64_t qi) {
     const int in = p.d + 3;
-    const float d0 = key_dist(pool[0]);
-    const float d9 = key_dist(pool[size > 10 ? 9 : size - 1]);
+    const float *sf = p.stop_f32;
+    asm volatile("" : "+s"(sf));   // not hoisted out of the search loop
     for (int i = lane; i < in; i += 64) {
         float f;
         if (i < p.d) f = q[i];
         else if (i == p.d) f = d0;
         else if (i == p.d + 1) f = d9 > 0.0f ? d0 / d9 : 1.0f;
         else f = (float)hops;
-        if (p.features) p.features[qi * (int64_t)in + i] = f;
-        if (p.learned) xbuf[i] = (f - p.stop_f32[i]) * p.stop_f32[in + i];
+        if (WF && p.features) p.features[qi * (int64_t)in + i] = f;
+        if (p.learned) xbuf[i] = (f - sf[i]) * sf[in + i];
     }
     wave_sync();
 }
@@ -140,23 +138,28 @@ __device__ inline void stop_features(const KParams &p, const float *q, const uin
 // accumulate) -> y = log2 pool size -> L_hat on the grid
 __device__ inline int stop_predict(const KParams &p, int Lq, int kq, const float *xbuf, int lane) {
     const int in = p.s_in, h = p.s_h;
-    const float *b1 = p.stop_f32 + 2 * in;
+    // the model is the same for every query: opaque base pointers keep the
+    // compiler from hoisting its loads out of the search loop (they would
+    // hold registers through every expansion)
+    const float *sf = p.stop_f32;
+    const _Float16 *W1T = p.stop_w;
+    asm volatile("" : "+s"(sf), "+s"(W1T));
+    const float *b1 = sf + 2 * in;
     const float *b2 = b1 + h;
     const float b3 = b2[h];
-    const _Float16 *W1T = p.stop_w;
     const _Float16 *W2T = W1T + (int64_t)in * h;
     const _Float16 *W3 = W2T + (int64_t)h * h;
     float a1 = 0.0f;
     if (lane < h) {
         float s = b1[lane];
-#pragma unroll 16
+#pragma unroll 4
         for (int i = 0; i < in; ++i) s = fmaf((float)W1T[(int64_t)i * h + lane], xbuf[i], s);
         a1 = s > 0.0f ? s : 0.0f;
     }
     float a2 = 0.0f;
     {
         float s = lane < h ? b2[lane] : 0.0f;
-#pragma unroll 16
+#pragma unroll 4
         for (int j = 0; j < h; ++j) {
             float aj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a1), j));
             if (lane < h) s = fmaf((float)W2T[j * h + lane], aj, s);
@@ -183,30 +186,33 @@ __device__ inline int stop_predict(const KParams &p, int Lq, int kq, const float
     return pick;
 }
 
-// FULL = false compiles the plain search only (no early stop, feature capture,
-// visited recording, pool output, counters or row prefetch): far less live
-// uniform state in the loop, so the scalar registers do not spill.
-template <int DT, int LPR, int CPL, bool FULL>
+// MODE selects what is compiled in: 0 the plain search only; 1 also the
+// learned early stop (and the chosen pool size output); 2 every option
+// (feature capture, visited recording, pool output, counters,
+// own-row visit).  Options left out keep registers free for occupancy.
+// NCH: pool chunks of 64 held in registers (NCH * 64 >= L_alloc).
+template <int DT, int LPR, int CPL, int MODE, int NCH>
 __global__ void __launch_bounds__(256) search_kernel(KParams p) {
     constexpr int EPC = Fmt<DT>::EPC;
+    constexpr bool FULL = MODE == 2;
+    constexpr bool LEARN = MODE >= 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int wpb = blockDim.x >> 6;
     unsigned char *wbase = smem + (size_t)wave * p.lds_per_wave;
     uint64_t *pool = reinterpret_cast<uint64_t *>(wbase);
     uint32_t *hash = reinterpret_cast<uint32_t *>(pool + p.L_alloc);
-    uint32_t *cid = hash + (1 << p.hash_bits);
-    float *cdist = reinterpret_cast<float *>(cid + kMaxR);
-    uint64_t *sbuf = reinterpret_cast<uint64_t *>(cdist + kMaxR);   // 16 staged keys (+16 spare)
-    float *xbuf = reinterpret_cast<float *>(sbuf + 32);
+    uint32_t *cid = hash + (1 << p.hash_bits);          // candidate ids
+    float *cdist = reinterpret_cast<float *>(cid + kMaxR);   // and distances
+    float *xbuf = cdist + kMaxR;                              // early-stop features
     const int H = 1 << p.hash_bits;
 
     int64_t qi;
     if (p.counter) {
         unsigned int t = 0;
         if (lane == 0) t = atomicAdd(p.counter, 1u);
-        qi = __shfl((int)t, 0);
+        qi = __builtin_amdgcn_readfirstlane((int)t);
     } else {
         qi = (int64_t)blockIdx.x * wpb + wave;
     }
@@ -216,7 +222,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
         kq = kq < 0 ? 0 : (kq > p.out_stride ? p.out_stride : kq);
         int Lq = p.L_arr ? p.L_arr[qi] : p.L_scalar;
         Lq = Lq < 1 ? 1 : (Lq > p.L_cap ? p.L_cap : Lq);
-        const bool learned = FULL && p.learned && Lq >= 16;
+        const bool learned = LEARN && p.learned && Lq >= 16;
         int Lcur = learned ? p.L_cap : Lq;
 
         // query chunks in registers, aligned with the row chunks this lane reads
@@ -241,7 +247,6 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
         const uint32_t start = p.start;
         int64_t hops = 0, nd = 0, ne = 0;
         int vcount = 0;
-        int size = 0;
         const bool rec = FULL && p.vis_ids != nullptr;
 
         // pool <- {start}
@@ -255,33 +260,23 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
             p.vis_dist[qi * (int64_t)p.vis_cap + vcount] = cdist[0];
         }
         vcount = 1;
-        if (lane == 0) pool[0] = mk_key(cdist[0], start);
-        size = 1;
-        wave_sync();
-        int cursor = 0;
+        RegPool<NCH> P;
+        rp_init<NCH>(P);
+        rp_insert<NCH>(P, readfirstlane64(mk_key(cdist[0], start)), Lcur, lane);
         bool stopped = !learned && !(FULL && p.features);   // true once the decision hop has passed
-        // neighbour row of the predicted next expansion, loaded during the merge
-        uint32_t pre_v = NSG_SENT, pre_u0 = NSG_SENT, pre_u1 = NSG_SENT;
-
         for (;;) {
-            int i = find_unchecked(pool, cursor, size, lane);
+            // Algorithm 1: expand the first unchecked pool entry
+            uint64_t pe;
+            const int i = rp_first_unchecked<NCH>(P, &pe);
             if (i < 0) break;
-            uint64_t pe = pool[i];
-            wave_sync();
-            if (lane == 0) pool[i] = pe | CHECKED_BIT;
+            rp_mark_checked<NCH>(P, i);
             uint32_t v = key_id(pe);
             v = v < p.n_rows ? v : 0u;
             ++hops;
             // neighbour ids (one coalesced row), visited filter, compaction
             const uint32_t *grow = p.graph + (int64_t)v * p.R_pad;
-            uint32_t row0, row1;
-            if (FULL && v == pre_v) {
-                row0 = pre_u0;
-                row1 = pre_u1;
-            } else {
-                row0 = lane < p.R ? grow[lane] : NSG_SENT;
-                row1 = lane + 64 < p.R ? grow[lane + 64] : NSG_SENT;
-            }
+            const uint32_t row0 = lane < p.R ? grow[lane] : NSG_SENT;
+            const uint32_t row1 = lane + 64 < p.R ? grow[lane + 64] : NSG_SENT;
             int cnt = 0;
             for (int b = 0; b < p.R; b += 64) {
                 uint32_t u = b == 0 ? row0 : row1;
@@ -293,10 +288,10 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
                 cnt += __popcll(bm);
             }
             wave_sync();
+            nd += cnt;
             if (cnt > 0) {
                 gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, p.n_rows, qv, sc, cid, cdist, cnt, lane);
                 wave_sync();
-                nd += cnt;
                 if (rec) {
                     for (int r = lane; r < cnt; r += 64)
                         if (vcount + r < p.vis_cap) {
@@ -304,68 +299,33 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
                             p.vis_dist[qi * (int64_t)p.vis_cap + vcount + r] = cdist[r];
                         }
                 }
-                vcount += cnt;
-                if (FULL && p.prefetch) {
-                    // the next expansion is the better of the best new key that
-                    // enters the pool and the first unchecked entry after i
-                    const uint64_t worst0 = size >= Lcur ? (pool[Lcur - 1] & KEY_MASK) : KEY_NONE;
-                    uint64_t kb = KEY_NONE;
-                    for (int r = lane; r < cnt; r += 64) {
-                        uint64_t kk = mk_key(cdist[r], cid[r]);
-                        kb = kk < kb ? kk : kb;
-                    }
-#pragma unroll
-                    for (int off = 32; off > 0; off >>= 1) {
-                        uint64_t o = shfl_xor64(kb, off);
-                        kb = o < kb ? o : kb;
-                    }
-                    int j = find_unchecked(pool, i + 1, size, lane);
-                    uint64_t kj = j >= 0 ? (pool[j] & KEY_MASK) : KEY_NONE;
-                    uint64_t kn = (kb < worst0 && kb < kj) ? kb : kj;
-                    if (kn != KEY_NONE) {
-                        pre_v = key_id(kn);
-                        const uint32_t *nrow = p.graph + (int64_t)pre_v * p.R_pad;
-                        pre_u0 = lane < p.R ? nrow[lane] : NSG_SENT;
-                        pre_u1 = lane + 64 < p.R ? nrow[lane + 64] : NSG_SENT;
-                    }
-                }
-                // keep candidates below the current L-th key, merge in rounds of 64
-                int first = size;
-                for (int b = 0; b < cnt; b += 64) {
-                    const uint64_t worst = size >= Lcur ? (pool[Lcur - 1] & KEY_MASK) : KEY_NONE;
-                    int r = b + lane;
-                    uint64_t key = KEY_NONE;
-                    if (r < cnt) {
-                        uint64_t kk = mk_key(cdist[r], cid[r]);
-                        if (kk < worst) key = kk;
-                    }
-                    int fi;
-                    size = merge_pool(pool, size, Lcur, key, sbuf, lane, &fi);
-                    first = fi < first ? fi : first;
-                }
-                cursor = (i + 1) < first ? (i + 1) : first;
-            } else {
-                cursor = i + 1;
+                merge_cands<NCH>(P, cid, cdist, cnt, Lcur, lane);
+                wave_sync();
             }
-            if (FULL && !stopped && hops >= p.s_hop) {
+            vcount += cnt;
+            if (LEARN && !stopped && hops >= p.s_hop) {
                 stopped = true;
-                stop_features(p, q, pool, size, hops, xbuf, lane, qi);
+                const float d0 = key_dist(rp_get<NCH>(P, 0));
+                const float d9 = key_dist(rp_get<NCH>(P, P.size > 10 ? 9 : P.size - 1));
+                stop_features<FULL>(p, q, d0, d9, hops, xbuf, lane, qi);
                 if (learned) {
                     Lcur = stop_predict(p, Lq, kq, xbuf, lane);
-                    if (size > Lcur) size = Lcur;
-                    if (cursor > size) cursor = size;
+                    rp_truncate<NCH>(P, Lcur, lane);
                 }
             }
         }
-        if (FULL && !stopped) {
+        if (LEARN && !stopped) {
             // ended before the decision point: the result equals the plain one
-            if (p.features)
+            if (FULL && p.features)
                 for (int t = lane; t < p.d + 3; t += 64) p.features[qi * (int64_t)(p.d + 3) + t] = NAN;
             if (learned) {
                 Lcur = Lq;
-                if (size > Lcur) size = Lcur;
+                rp_truncate<NCH>(P, Lcur, lane);
             }
         }
+        rp_store<NCH>(P, pool, lane);
+        const int size = P.size;
+        wave_sync();
         if (FULL && p.self_offset >= 0) {
             // index build: also visit the query node's own row (its kNN list)
             const uint32_t self = (uint32_t)(p.self_offset + qi);
@@ -414,25 +374,29 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
             if (p.hops) p.hops[qi] = hops;
             if (p.ndist) p.ndist[qi] = nd;
             if (p.nedges) p.nedges[qi] = ne;
-            if (p.L_used) p.L_used[qi] = Lcur;
             if (p.vis_cnt) p.vis_cnt[qi] = vcount;
         }
+        if (LEARN && lane == 0 && p.L_used) p.L_used[qi] = Lcur;
         wave_sync();
         if (!p.counter) break;
         unsigned int t = 0;
         if (lane == 0) t = atomicAdd(p.counter, 1u);
-        qi = __shfl((int)t, 0);
+        qi = __builtin_amdgcn_readfirstlane((int)t);
     }
 }
 
 
 typedef void (*kfn_t)(KParams);
 
-template <int DT>
-static kfn_t pick_kernel_t(int lpr, int cpl, bool full) {
-#define NSG_K(L_, C_)                                                              \
-    if (lpr == L_ && cpl == C_) return full ? search_kernel<DT, L_, C_, true>      \
-                                            : search_kernel<DT, L_, C_, false>;
+// Kernel for a layout (lanes per row, chunks per lane), a MODE and nch pool
+// chunks of 64 held in registers (2, 4 or 8: pool capacity <= 128, 256, 512).
+// Each per-format source instantiates one MODE.
+template <int DT, int MODE>
+static kfn_t pick_kernel_t(int lpr, int cpl, int nch) {
+#define NSG_K(L_, C_)                                                                   \
+    if (lpr == L_ && cpl == C_)                                                         \
+        return nch <= 2 ? search_kernel<DT, L_, C_, MODE, 2>                          \
+                        : nch <= 4 ? search_kernel<DT, L_, C_, MODE, 4> : search_kernel<DT, L_, C_, MODE, 8>;
     NSG_K(8, 1) NSG_K(8, 2) NSG_K(8, 4)
     NSG_K(16, 1) NSG_K(16, 2) NSG_K(16, 4)
     NSG_K(32, 1) NSG_K(32, 2) NSG_K(32, 4)

@@ -89,6 +89,25 @@ __device__ inline uint64_t mk_key(float d, uint32_t id) {
 __device__ inline float key_dist(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
 __device__ inline uint32_t key_id(uint64_t k) { return (uint32_t)(k & 0x7FFFFFFFu); }
 
+// Sum over aligned groups of G lanes (G a power of two <= 64); every lane of
+// a group receives its group's sum.  Within a row of 16 lanes the steps are
+// DPP moves (mirror, half-mirror, quad permutations), across rows lane
+// shuffles.
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int G>
+__device__ inline float group_sum(float s) {
+    if (G >= 64) s += __shfl_xor(s, 32);
+    if (G >= 32) s += __shfl_xor(s, 16);
+    if (G >= 16) s += dpp_mov<0x140>(s);   // row_mirror: lane l <-> 15 - l
+    if (G >= 8) s += dpp_mov<0x141>(s);    // row_half_mirror: lane l <-> 7 - l
+    if (G >= 4) s += dpp_mov<0x4E>(s);     // quad_perm [2,3,0,1]
+    if (G >= 2) s += dpp_mov<0xB1>(s);     // quad_perm [1,0,3,2]
+    return s;
+}
+
 // ascending bitonic sort of one key per lane across the 64 lanes
 __device__ inline uint64_t wave_sort64(uint64_t key, int lane) {
 #pragma unroll
@@ -148,17 +167,18 @@ __device__ inline uint64_t readfirstlane64(uint64_t v) {
 }
 
 // Merge the M keys staged in sbuf[0..M) (KEY_NONE = empty) into the sorted
-// pool of `size` entries, keeping the first Lcur.
+// pool of `size` entries (size and Lcur wave-uniform), keeping the first Lcur.
 //
 // The staged keys are read back as wave-uniform values, so every step is a
 // fixed, unrolled set of independent compares and ballots (no loop whose trip
 // count depends on the data).  A staged key is dropped if an earlier staged
 // key equals it (a node recorded twice) or if the pool holds it (a node the
-// visited filter forgot; the pool entry keeps its checked flag).  For each
-// kept key j: lb_j = #pool keys below it, rank_j = #kept keys below it; pool
-// entry i moves to i + #{kept keys below it} (chunks last first, so nothing is
-// overwritten before it is read) and key j goes to lb_j + rank_j.  Positions
-// at or beyond Lcur are not written.
+// visited filter forgot; the pool entry keeps its checked flag): lane j looks
+// at the pool entry at key j's lower bound, the only place an equal key can
+// sit.  For each kept key j: lb_j = #pool keys below it; pool entry i moves to
+// i + #{kept keys below it} (chunks last first, so nothing is overwritten
+// before it is read) and key j goes to lb_j + #{kept keys below it}.
+// Positions at or beyond Lcur are not written.
 template <int M>
 __device__ int merge_staged(uint64_t *pool, int size, int Lcur, const uint64_t *sbuf, int lane,
                             int *first_ins) {
@@ -166,10 +186,10 @@ __device__ int merge_staged(uint64_t *pool, int size, int Lcur, const uint64_t *
 #pragma unroll
     for (int j = 0; j < M; ++j) bk[j] = readfirstlane64(sbuf[j]);
     const uint64_t mine = lane < M ? sbuf[lane] : KEY_NONE;
-    bool dup = false;
+    uint64_t dup = 0;
 #pragma unroll
-    for (int j = 0; j < M - 1; ++j) dup |= (j < lane) && bk[j] == mine;
-    uint32_t keep = (uint32_t)__ballot(mine != KEY_NONE && !dup);
+    for (int j = 0; j < M - 1; ++j) dup |= __ballot(mine == bk[j]) & (~0ull << (j + 1));
+    uint32_t keep = (uint32_t)(__ballot(mine != KEY_NONE) & ~dup);
     const int nch = (size + 63) >> 6;
     int lb[M];
 #pragma unroll
@@ -178,16 +198,22 @@ __device__ int merge_staged(uint64_t *pool, int size, int Lcur, const uint64_t *
         const int i = (c << 6) + lane;
         const uint64_t pk = i < size ? (pool[i] & KEY_MASK) : KEY_NONE;
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            lb[j] += __popcll(__ballot(pk < bk[j]));
-            if (__ballot(pk == bk[j])) keep &= ~(1u << j);
-        }
+        for (int j = 0; j < M; ++j) lb[j] += __popcll(__ballot(pk < bk[j]));
     }
+    int mylb = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) mylb = lane == j ? lb[j] : mylb;
+    bool eq = false;
+    if (lane < M && ((keep >> lane) & 1u) && mylb < size) eq = (pool[mylb] & KEY_MASK) == mine;
+    keep &= ~(uint32_t)__ballot(eq);
     if (!keep) return size;
     int p0 = size;
 #pragma unroll
-    for (int j = 0; j < M; ++j)
-        if ((keep >> j) & 1u) p0 = lb[j] < p0 ? lb[j] : p0;
+    for (int j = 0; j < M; ++j) {
+        const bool kj = (keep >> j) & 1u;
+        if (!kj) bk[j] = KEY_NONE;   // a dropped key shifts nothing
+        p0 = (kj && lb[j] < p0) ? lb[j] : p0;
+    }
     if (p0 >= Lcur) return size;
     // pool entries [p0, size) move right, last chunk first
     for (int c = nch - 1; c >= 0 && (c << 6) + 63 >= p0; --c) {
@@ -197,18 +223,15 @@ __device__ int merge_staged(uint64_t *pool, int size, int Lcur, const uint64_t *
         const uint64_t vk = v & KEY_MASK;
         int sh = 0;
 #pragma unroll
-        for (int j = 0; j < M; ++j) sh += (((keep >> j) & 1u) && bk[j] < vk) ? 1 : 0;
+        for (int j = 0; j < M; ++j) sh += bk[j] < vk ? 1 : 0;
         wave_sync();
         if (act && i + sh < Lcur) pool[i + sh] = v;
         wave_sync();
     }
     // kept staged keys: lane j places key j
-    int pos = 0;
+    int pos = mylb;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        pos += (((keep >> j) & 1u) && bk[j] < mine) ? 1 : 0;
-        pos += lane == j ? lb[j] : 0;
-    }
+    for (int j = 0; j < M; ++j) pos += bk[j] < mine ? 1 : 0;
     if (lane < M && ((keep >> lane) & 1u) && pos < Lcur) pool[pos] = mine;
     wave_sync();
     *first_ins = p0;
@@ -249,53 +272,259 @@ __device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key, uint
     return size;
 }
 
+// ------------------------------------------------------------------------
+// register-resident pool (search)
+// ------------------------------------------------------------------------
+// Lane l of pk[c] holds the key of pool entry 64c + l (KEY_NONE at or beyond
+// size); bit l of the wave-uniform mask chk[c] is that entry's checked flag.
+// The pool is sorted by key, so Algorithm 1's "first unchecked" is a scalar
+// bit scan and an insertion is one compare + ballot per chunk (the rank)
+// followed by a one-lane shift of the chunks at or above it.
+template <int NCH>
+struct RegPool {
+    uint64_t pk[NCH];
+    uint64_t chk[NCH];
+    int size;
+};
+
+// whole-wave shift by one lane towards higher lanes (lane 0 receives 0)
+__device__ __attribute__((always_inline)) inline uint64_t wave_shr64(uint64_t v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v & 0xFFFFFFFFu), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <int NCH>
+__device__ __attribute__((always_inline)) inline void rp_init(RegPool<NCH> &P) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        P.pk[c] = KEY_NONE;
+        P.chk[c] = 0ull;
+    }
+    P.size = 0;
+}
+
+// key of entry pos (wave-uniform, < NCH * 64)
+template <int NCH>
+__device__ __attribute__((always_inline)) inline uint64_t rp_get(const RegPool<NCH> &P, int pos) {
+    // read lane pos & 63 of every chunk, keep chunk pos >> 6 (scalar selects;
+    // selecting the registers first would index the chunk array dynamically)
+    const int cw = pos >> 6, l = pos & 63;
+    uint64_t v = KEY_NONE;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const uint64_t x = readlane64(P.pk[c], l);
+        v = cw == c ? x : v;
+    }
+    return v;
+}
+
+// position of the first unchecked entry (-1 if none); its key in *key
+template <int NCH>
+__device__ __attribute__((always_inline)) inline int rp_first_unchecked(const RegPool<NCH> &P, uint64_t *key) {
+    int pos = -1;
+#pragma unroll
+    for (int c = NCH - 1; c >= 0; --c) {
+        const int n = P.size - (c << 6);
+        const uint64_t valid = n >= 64 ? ~0ull : (n > 0 ? ((1ull << n) - 1ull) : 0ull);
+        const uint64_t um = valid & ~P.chk[c];
+        pos = um ? (c << 6) + __builtin_ctzll(um) : pos;
+    }
+    if (pos >= 0) *key = rp_get<NCH>(P, pos);
+    return pos;
+}
+
+template <int NCH>
+__device__ __attribute__((always_inline)) inline void rp_mark_checked(RegPool<NCH> &P, int pos) {
+    const uint64_t bit = 1ull << (pos & 63);
+    const int cw = pos >> 6;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) P.chk[c] |= (uint64_t)(cw == c) * bit;
+}
+
+// Insert the wave-uniform key s unless the pool holds it (a node the visited
+// filter forgot) or it ranks at or beyond Lcur; entries pushed past Lcur are
+// dropped.  Returns true if inserted.
+template <int NCH>
+__device__ __attribute__((always_inline)) inline bool rp_insert(RegPool<NCH> &P, uint64_t s, int Lcur, int lane) {
+    int lt = 0;
+    bool eq = false;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        if ((c << 6) < P.size) {
+            lt += __popcll(__ballot(P.pk[c] < s));
+            eq |= __ballot(P.pk[c] == s) != 0ull;
+        }
+    }
+    if (eq || lt >= Lcur) return false;
+    const int top = P.size < Lcur ? P.size : Lcur - 1;   // last occupied position afterwards
+#pragma unroll
+    for (int c = NCH - 1; c >= 0; --c) {
+        if ((c << 6) > top || (c << 6) + 63 < lt) continue;
+        // chunk c-1 is still unmodified: its last entry moves into lane 0
+        const uint64_t carry = c > 0 ? readlane64(P.pk[c > 0 ? c - 1 : 0], 63) : KEY_NONE;
+        const uint64_t cbit = c > 0 ? (P.chk[c > 0 ? c - 1 : 0] >> 63) : 0ull;
+        uint64_t sh = wave_shr64(P.pk[c]);
+        sh = lane == 0 ? carry : sh;
+        const int idx = (c << 6) + lane;
+        uint64_t nv = idx > lt ? sh : (idx == lt ? s : P.pk[c]);
+        P.pk[c] = idx > top ? KEY_NONE : nv;
+        const int lo = lt - (c << 6);
+        const uint64_t f = P.chk[c];
+        if (lo <= 0) {
+            P.chk[c] = (f << 1) | (lo < 0 ? cbit : 0ull);
+        } else {
+            const uint64_t below = (1ull << lo) - 1ull;
+            const uint64_t above = ~((2ull << lo) - 1ull);
+            P.chk[c] = (f & below) | ((f << 1) & above);
+        }
+    }
+    P.size = P.size < Lcur ? P.size + 1 : Lcur;
+    return true;
+}
+
+// drop entries at or beyond n
+template <int NCH>
+__device__ __attribute__((always_inline)) inline void rp_truncate(RegPool<NCH> &P, int n, int lane) {
+    if (P.size <= n) return;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        if ((c << 6) + lane >= n) P.pk[c] = KEY_NONE;
+    P.size = n;
+}
+
+// write the pool to LDS (checked flag in the key's flag bit)
+template <int NCH>
+__device__ __attribute__((always_inline)) inline void rp_store(const RegPool<NCH> &P, uint64_t *pool, int lane) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int idx = (c << 6) + lane;
+        if ((c << 6) < P.size && idx < P.size)
+            pool[idx] = P.pk[c] | (((P.chk[c] >> lane) & 1ull) ? CHECKED_BIT : 0ull);
+    }
+}
+
+// rows of one gather round
+template <int LPR, int CPL>
+struct GatherShape {
+    static constexpr int RPP = 64 / LPR;                          // rows per pass
+    static constexpr int U = (8 / CPL) > 0 ? (8 / CPL) : 1;       // passes per round
+    static constexpr int ROWS = RPP * U;
+};
+
+// One gather round, split in two so that other work can run while its loads
+// are in flight.  gather_issue reads the row ids cid[r], r = r0 + u * RPP +
+// lane / LPR (u < U), in one LDS round trip and issues every row load (rows at
+// or beyond cnt are not loaded); gather_finish turns the loaded chunks into
+// squared distances to q, which every lane of a row group receives.
+template <int DT, int LPR, int CPL>
+struct GatherRaw {
+    uint4 raw[GatherShape<LPR, CPL>::U][CPL];
+    uint32_t ids[GatherShape<LPR, CPL>::U];
+};
+
+template <int DT, int LPR, int CPL>
+__device__ __attribute__((always_inline)) inline void gather_issue(const uint4 *rows, int row_chunks,
+                                                                   uint32_t n_rows, const uint32_t *cid, int r0,
+                                                                   int cnt, int lane, GatherRaw<DT, LPR, CPL> &G) {
+    constexpr int RPP = GatherShape<LPR, CPL>::RPP;
+    constexpr int U = GatherShape<LPR, CPL>::U;
+    const int g = lane / LPR, li = lane % LPR;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = r0 + u * RPP + g;
+        G.ids[u] = cid[r < kMaxR ? r : kMaxR - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool ok = r0 + u * RPP + g < cnt;
+        const uint32_t iu = G.ids[u] < n_rows ? G.ids[u] : 0u;     // never index past the base
+        const uint4 *row = rows + (int64_t)iu * row_chunks;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            int ch = li + c * LPR;
+            G.raw[u][c] = (ok && ch < row_chunks) ? row[ch] : make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+}
+
+template <int DT, int LPR, int CPL>
+__device__ __attribute__((always_inline)) inline void gather_finish(const float (&qv)[CPL][Fmt<DT>::EPC],
+                                                                    const float (&sc)[CPL][Fmt<DT>::EPC],
+                                                                    const GatherRaw<DT, LPR, CPL> &G,
+                                                                    float (&dist)[GatherShape<LPR, CPL>::U]) {
+    constexpr int EPC = Fmt<DT>::EPC;
+    constexpr int U = GatherShape<LPR, CPL>::U;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            float x[EPC];
+            Fmt<DT>::dec(G.raw[u][c], x);
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                float xv = DT == NSG_F32 ? x[e] : sc[c][e] * x[e];
+                float t = qv[c][e] - xv;
+                acc = fmaf(t, t, acc);
+            }
+        }
+        dist[u] = group_sum<LPR>(acc);
+    }
+}
+
+// distances of one round -> cdist[r] (one lane per row)
+template <int LPR, int CPL>
+__device__ __attribute__((always_inline)) inline void store_round(const float (&dist)[GatherShape<LPR, CPL>::U],
+                                                                  float *cdist, int r0, int cnt, int lane) {
+    constexpr int RPP = GatherShape<LPR, CPL>::RPP;
+    constexpr int U = GatherShape<LPR, CPL>::U;
+    const int g = lane / LPR, li = lane % LPR;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = r0 + u * RPP + g;
+        if (li == 0 && r < cnt) cdist[r] = dist[u];
+    }
+}
+
 // squared distances of q to the rows cid[0..cnt) (search format) -> cdist
 template <int DT, int LPR, int CPL>
 __device__ inline void gather_dist(const uint4 *rows, int row_chunks, uint32_t n_rows,
                                    const float (&qv)[CPL][Fmt<DT>::EPC],
                                    const float (&sc)[CPL][Fmt<DT>::EPC],
                                    const uint32_t *cid, float *cdist, int cnt, int lane) {
-    constexpr int EPC = Fmt<DT>::EPC;
-    constexpr int RPP = 64 / LPR;
-    constexpr int U = (8 / CPL) > 0 ? (8 / CPL) : 1;
-    const int g = lane / LPR, li = lane % LPR;
-    for (int r0 = 0; r0 < cnt; r0 += RPP * U) {
-        uint4 raw[U][CPL];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            int r = r0 + u * RPP + g;
-            bool ok = r < cnt;
-            uint32_t id = ok ? cid[r] : 0u;
-            id = id < n_rows ? id : 0u;     // never index past the base
-            const uint4 *row = rows + (int64_t)id * row_chunks;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                int ch = li + c * LPR;
-                raw[u][c] = (ok && ch < row_chunks) ? row[ch] : make_uint4(0u, 0u, 0u, 0u);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                float x[EPC];
-                Fmt<DT>::dec(raw[u][c], x);
-#pragma unroll
-                for (int e = 0; e < EPC; ++e) {
-                    float xv = DT == NSG_F32 ? x[e] : sc[c][e] * x[e];
-                    float t = qv[c][e] - xv;
-                    acc = fmaf(t, t, acc);
-                }
-            }
-#pragma unroll
-            for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-            int r = r0 + u * RPP + g;
-            if (li == 0 && r < cnt) cdist[r] = acc;
-        }
-        if (r0 + RPP * U >= cnt) break;
+    constexpr int ROWS = GatherShape<LPR, CPL>::ROWS;
+    for (int r0 = 0; r0 < cnt; r0 += ROWS) {
+        GatherRaw<DT, LPR, CPL> G;
+        float dist[GatherShape<LPR, CPL>::U];
+        gather_issue<DT, LPR, CPL>(rows, row_chunks, n_rows, cid, r0, cnt, lane, G);
+        gather_finish<DT, LPR, CPL>(qv, sc, G, dist);
+        store_round<LPR, CPL>(dist, cdist, r0, cnt, lane);
     }
 }
 
+// Merge the candidates (cid[r], cdist[r]), r < cnt, into the pool: those
+// below the current L-th key are inserted one by one (rp_insert drops keys the
+// pool holds and keys pushed to rank Lcur or beyond).
+template <int NCH>
+__device__ __attribute__((always_inline)) inline void merge_cands(RegPool<NCH> &P, const uint32_t *cid,
+                                                                  const float *cdist, int cnt, int Lcur,
+                                                                  int lane) {
+    for (int b = 0; b < cnt; b += 64) {
+        const uint64_t worst = P.size >= Lcur ? rp_get<NCH>(P, Lcur - 1) : KEY_NONE;
+        const int r = b + lane;
+        uint64_t key = KEY_NONE;
+        if (r < cnt) {
+            const uint64_t kk = mk_key(cdist[r], cid[r]);
+            if (kk < worst) key = kk;
+        }
+        uint64_t sm = __ballot(key != KEY_NONE);
+        while (sm) {
+            const int l = __builtin_ctzll(sm);
+            sm &= sm - 1ull;
+            rp_insert<NCH>(P, readlane64(key, l), Lcur, lane);
+        }
+    }
+}
 
 }  // namespace nsg

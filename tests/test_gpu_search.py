@@ -193,20 +193,6 @@ def test_layouts_agree(tiny_gpu, nsg, lpr):
     assert r["ok"], r
 
 
-def test_prefetch_results_unchanged(tiny_gpu, nsg):
-    """Loading the predicted next row early changes no result or count."""
-    t = tiny_gpu
-    outs = []
-    for pf in (-1, 1):
-        hops = torch.zeros(len(t["Q"]), dtype=torch.int64, device=t["Qd"].device)
-        nd = torch.zeros_like(hops)
-        ids, dist = nsg.search_batched(t["ix"], t["Qd"], k_scalar=10, L_scalar=80,
-                                       opts=dict(prefetch=pf, hops=hops, ndist=nd))
-        outs.append((ids, dist, hops, nd))
-    for a, b in zip(outs[0], outs[1]):
-        assert (a == b).all()
-
-
 def test_repeated_ids_and_tiny_filter_regression(tiny_gpu, nsg):
     """Rows that repeat ids, searched with a 64-slot visited filter: nodes are
     recomputed and offered twice in one merge batch; results still equal the
