@@ -7,7 +7,9 @@ Pipeline (everything on the GPU through libnsg.so, outside the timed region):
   build     NSG (Algorithm 2: R=50, l=40, C=500) on the GPU
   truth     exact top-100 of the test queries (brute force)
   sweep     plain FP32 search over L -> the smallest L with mean recall@10 >= 0.95
-  learned   traces on the FP16 index, labels, MLP training, calibration
+  learned   per-query expansion budgets at FP16 pool sizes L16, 1.25 L16, 1.5 L16
+            (L16: the plain FP16 one): budget traces, labels, MLP training and
+            calibration each; the fastest on held-out training queries is kept
 Timed: `--warmup` untimed steps, then `--steps` steps; a step is one search
 call over the whole 10k-query batch (queries already resident in HBM), for
 each of the two configurations.  Prints ONE JSON line.
@@ -44,8 +46,6 @@ def main():
     ap.add_argument("--train", type=int, default=200_000)
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--grid-max", type=int, default=181,
-                    help="largest pool size the learned stop may pick (bounds the slowest query of a batch)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="sift1m_like", choices=["sift1m_like", "deep_uneven"],
                     help="deep_uneven: DEEP-like unit vectors, 100k queries with uneven k and L served in "
@@ -146,38 +146,74 @@ def main():
     L32 = f32[0]
 
     # ---------------- learned early stop (FP16 index) ----------------
+    # The early stop gives each query an expansion budget at a fixed pool size.
+    # Pool sizes at and above the plain FP16 one are tried; each gets its own
+    # traces, network and calibration on held-out training queries, and the
+    # fastest on held-out training queries (never the test queries) is kept.
     ntr = args.train
     Tq = torch.from_numpy(datagen.train_queries(w, ntr)).to(dev)
     ttruth, _ = nsg.knn_bruteforce(Xd, Tq, k)
-    t = time.time()
-    tr = ls.traces(ix16, Tq, ttruth, k=k)
-    torch.cuda.synchronize()
-    y, reached = ls.labels(tr, k)
-    hist = np.bincount(np.searchsorted(tr.grid, np.exp2(y).round()), minlength=len(tr.grid))
-    log(f"traces: {ntr} queries x {len(tr.grid)} pool sizes in {time.time() - t:.1f}s; "
-        f"reached exact top-{k}: {reached.mean():.3f}; label histogram over {tr.grid}: {hist.tolist()}")
     n_fit = int(ntr * 0.9)
-    t = time.time()
-    P, mean, istd = ls.train(tr.features[:n_fit].contiguous(), y[:n_fit], seed=7, epochs=30,
-                             log=None)
-    torch.cuda.synchronize()
-    log(f"MLP trained in {time.time() - t:.1f}s")
-    yh = ls.predict(P, mean, istd, tr.features[n_fit:].contiguous()).cpu().numpy()
-    hold_mse = float(np.mean((yh - y[n_fit:]) ** 2))
-    base_mse = float(np.mean((y[n_fit:] - y[:n_fit].mean()) ** 2))
-    grid = [g for g in tr.grid if g <= args.grid_max]
-    cal = ls.calibrate(yh, tr.hits[n_fit:, :len(grid)].cpu().numpy(), grid, k, args.target, margin=0.005)
-    log(f"held-out MSE {hold_mse:.4f} (constant predictor {base_mse:.4f}); calibration {cal}")
-    c = cal[0] if cal else 4.0
+    hq = Tq[n_fit:].contiguous()
+    hq_truth = ttruth[n_fit:].contiguous()
+    L_base = f16[0] if f16 else 512
+    best = None
+    for L_l in sorted({L_base, int(round(L_base * 1.25)), int(round(L_base * 1.5))}):
+        L_l = min(L_l, 512)
+        t = time.time()
+        tr = ls.traces(ix16, Tq, ttruth, L_l, k=k)
+        torch.cuda.synchronize()
+        y, reached = ls.labels(tr, k)
+        hist = np.bincount(np.searchsorted(tr.grid, np.exp2(y).round()), minlength=len(tr.grid))
+        log(f"L={L_l}: traces {ntr} queries x {len(tr.grid)} budgets in {time.time() - t:.1f}s; mean expansions "
+            f"{tr.hops.float().mean().item():.1f}; converged within the grid: {reached.mean():.3f}; "
+            f"label histogram over {tr.grid}: {hist.tolist()}")
+        t = time.time()
+        P, mean, istd = ls.train(tr.features[:n_fit].contiguous(), y[:n_fit], seed=7, epochs=30, log=None)
+        torch.cuda.synchronize()
+        yh = ls.predict(P, mean, istd, tr.features[n_fit:].contiguous()).cpu().numpy()
+        hold_mse = float(np.mean((yh - y[n_fit:]) ** 2))
+        base_mse = float(np.mean((y[n_fit:] - y[:n_fit].mean()) ** 2))
+        cal = ls.calibrate(yh, tr.hits[n_fit:].cpu().numpy(), tr.grid, k, args.target, margin=0.003,
+                           hops=tr.hops[n_fit:].cpu().numpy())
+        log(f"L={L_l}: MLP trained in {time.time() - t:.1f}s; held-out MSE {hold_mse:.4f} (constant predictor "
+            f"{base_mse:.4f}); calibration (c, recall, mean budget, mean expansions) {cal}")
+        if not cal:
+            continue
+        ls.install(ix16, P, mean, istd, cal[0], tr.grid)
+        for hs in (1024, 2048):
+            o = dict(learned_stop=1, persistent=1, hash_slots=hs)
+            run = lambda: nsg.search_batched(ix16, hq, k_scalar=k, L_scalar=L_l, opts=o)
+            for _ in range(2):
+                run()
+            torch.cuda.synchronize()
+            t0 = time.time()
+            for _ in range(5):
+                ids, _ = run()
+            torch.cuda.synchronize()
+            ms = (time.time() - t0) / 5 * 1e3
+            hr = nsg.recall_hits(ids.view(len(hq), 1, k).contiguous(), hq_truth, k).float().mean().item() / k
+            log(f"L={L_l} hash {hs}: held-out training queries: {ms:.3f} ms per {len(hq)}, recall@10 {hr:.4f}")
+            if best is None or ms < best["ms"]:
+                best = dict(ms=ms, L=L_l, hs=hs, P=P, mean=mean, istd=istd, c=cal[0], grid=tr.grid,
+                            hold_mse=hold_mse, base_mse=base_mse, cal=cal)
+    if best is None:
+        print(json.dumps({"error": "the learned stop never reaches the target recall"}))
+        sys.exit(3)
+    L_fb, P, mean, istd, c, grid = best["L"], best["P"], best["mean"], best["istd"], best["c"], best["grid"]
+    hs_l = best["hs"]
+    hold_mse, base_mse = best["hold_mse"], best["base_mse"]
+    # test queries: recall check (c is raised if the held-out calibration falls short)
     learned = None
-    L_fb = f16[0] if f16 else 512          # fixed-L fallback of the learned mode
     for _ in range(12):
         ls.install(ix16, P, mean, istd, c, grid)
-        Lu = torch.empty(nq, dtype=torch.int32, device=dev)
+        Bu = torch.empty(nq, dtype=torch.int32, device=dev)
+        hq_h = torch.empty(nq, dtype=torch.int64, device=dev)
         ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L_fb,
-                                    opts=dict(learned_stop=1, L_used=Lu, persistent=1))
+                                    opts=dict(learned_stop=1, budget=Bu, hops=hq_h, persistent=1, hash_slots=hs_l))
         r = recall(ids)
-        learned = dict(c=c, recall=r, mean_L=float(Lu.float().mean().item()))
+        learned = dict(L=L_fb, hash_slots=hs_l, c=c, recall=r, mean_budget=float(Bu.float().mean().item()),
+                       mean_expansions=float(hq_h.float().mean().item()), heldout_calibration=best["cal"])
         if r >= args.target:
             break
         c *= 2 ** 0.25
@@ -245,7 +281,7 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
 
     def step16():
         nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L_fb, out_ids=out16[0], out_dist=out16[1],
-                           opts=dict(learned_stop=1, persistent=1))
+                           opts=dict(learned_stop=1, persistent=1, hash_slots=int((learned or {}).get("hash_slots", 0))))
 
     ms16, wall16 = timed(step16, args.steps, args.warmup)
     r16 = recall(out16[0])

@@ -116,7 +116,7 @@ typedef struct nsg_search_opts {
     int32_t rerank;          /* 0: default (on for reduced storage), 1: on, -1: off */
     int64_t *hops;           /* device [nq] expansions per query, or NULL */
     int64_t *ndist;          /* device [nq] distance evaluations per query, or NULL */
-    int32_t *L_used;         /* device [nq] pool size after the early stop, or NULL */
+    int32_t *budget;         /* device [nq] expansion budget chosen by the early stop (0: none), or NULL */
     float *features;         /* device [nq][d + 3] early-stop features (query, best pool
                                 distance, 1st/10th pool distance ratio, hops) right after
                                 expansion `feature_hop`; NaN rows for searches that ended
@@ -129,6 +129,7 @@ typedef struct nsg_search_opts {
     int32_t lanes_per_row;   /* lanes that gather one row (8, 16, 32, 64); 0: default */
     uint32_t *counter;       /* device scratch word for the persistent work counter (reset by the
                                 call); NULL: allocated per call (not usable under graph capture) */
+    int32_t max_hops;        /* > 0: every query stops after this many expansions; 0: no budget */
 } nsg_search_opts;
 
 /*
@@ -219,11 +220,14 @@ int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t *knn,
  * Network: in = d + 3 features (query, best pool distance, ratio of the 1st
  * to the 10th pool distance, hop count) taken after `hop` expansions,
  * z-scored with mean[in] / inv_std[in]; two ReLU hidden layers of h units;
- * one linear output y = predicted log2 of the pool size.  The pool is then
- * cut to L_hat = clamp(smallest grid value >= c * 2^y, max(16, k), 512) and
- * the search continues; a non-finite y falls back to the query's own L.
+ * one linear output y = predicted log2 of the expansion budget.  The query
+ * then stops after B = max(hop, smallest grid value >= c * 2^y) expansions
+ * (the largest grid value if none is), or earlier when no unchecked entry
+ * remains: its result is the plain search's after min(B, its own expansion
+ * count) expansions, with the same L.  A non-finite y sets no budget.
  * blob (host) holds FP32: mean[in], inv_std[in], W1[h][in], b1[h],
- * W2[h][h], b2[h], W3[h], b3, then `grid_n` FP32 grid values ascending.
+ * W2[h][h], b2[h], W3[h], b3, then `grid_n` FP32 grid values (expansion
+ * counts in [1, 2^20]) ascending.
  */
 int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes,
                         int32_t in, int32_t h, int32_t hop, int32_t grid_n);

@@ -61,7 +61,7 @@ def _get():
             "oracle_l2sq_f64": (f64, [P, P, i32]),
             "oracle_knn": (i32, [P, i64, i32, P, i64, i32, i32, i32, P, P]),
             "oracle_search_batch": (i32, [P, i64, i32, P, i32, u32, P, i64, i32, i32, P, P,
-                                          i32, P, P, P, P, P, P, i32, i64, P, i32]),
+                                          i32, P, P, P, P, P, P, i32, P, i32]),
             "oracle_search_one": (i32, [P, i64, i32, P, i32, u32, P, i32, i64, P, P, P,
                                         P, i64, P, P, i64, P]),
             "oracle_centroid": (i32, [P, i64, i32, P]),
@@ -137,9 +137,10 @@ def knn_graph(base, K):
 # --------------------------------------------------------------------------
 
 def search(base, graph, start, queries, k, L, k_arr=None, L_arr=None, pool_stride=0,
-           trunc_hop=-1, trunc_L=None, threads=0):
+           max_hops=None, threads=0):
     """Batched Algorithm 1 from `start`.  Returns (ids, dist, hops, ndist[, pool_ids,
-    pool_dist]).  With per-query k_arr / L_arr the outputs are [nq][max k]."""
+    pool_dist]).  With per-query k_arr / L_arr the outputs are [nq][max k].
+    max_hops: optional per-query expansion budget (<= 0: none)."""
     base, graph, queries = _f32(base), _u32(graph), _f32(queries)
     n, d = base.shape
     R = graph.shape[1]
@@ -155,11 +156,11 @@ def search(base, graph, start, queries, k, L, k_arr=None, L_arr=None, pool_strid
     if pool_stride:
         pids = np.empty((nq, pool_stride), np.uint32)
         pd = np.empty((nq, pool_stride), np.float32)
-    tl = None if trunc_L is None else np.ascontiguousarray(trunc_L, np.int32)
+    mh = None if max_hops is None else np.ascontiguousarray(np.broadcast_to(max_hops, (nq,)), np.int32)
     _check(_get().oracle_search_batch(
         _p(base), n, d, _p(graph), R, int(start), _p(queries), nq, int(k), int(L),
         _p(k_arr_c), _p(L_arr_c), kst, _p(ids), _p(dist), _p(hops), _p(nd),
-        _p(pids), _p(pd), int(pool_stride), int(trunc_hop), _p(tl), int(threads)), "search")
+        _p(pids), _p(pd), int(pool_stride), _p(mh), int(threads)), "search")
     if pool_stride:
         return ids, dist, hops, nd, pids, pd
     return ids, dist, hops, nd

@@ -212,9 +212,8 @@ static int ws_vis_push(ws_t *w, float dist, uint32_t id)
  *   - ties and truncation use the (distance, id) key.
  *   - k > |pool|: missing results are (SENT, +inf).
  * `stop_hop` >= 0 makes the search stop right after that many expansions
- * (used to read the pool state for the learned early-stop features).
- * `trunc_hop`/`trunc_L`: after trunc_hop expansions the pool capacity becomes
- * trunc_L (learned early termination; trunc_hop < 0 disables it).
+ * (an expansion budget: the learned early stop, and the pool state read for
+ * its features).
  * When `keep_visited` is set every visited node is appended to w->vis.
  * Returns the final pool size (>= 1).
  */
@@ -222,7 +221,6 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
                        uint32_t start, const float *q, int L, ws_t *w,
                        int64_t *hops_out, int64_t *ndist_out,
                        int keep_visited, int64_t stop_hop,
-                       int64_t trunc_hop, int trunc_L,
                        uint32_t *trace, int64_t trace_cap)
 {
     int64_t hops = 0, ndist = 0;
@@ -232,9 +230,7 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
         w->cur = 1;
     }
     w->vis_cnt = 0;
-    int Lcap = L;
-    if (trunc_hop >= 0 && trunc_L > Lcap) Lcap = trunc_L;
-    ws_pool_reserve(w, Lcap + R);
+    ws_pool_reserve(w, L + R);
     pent_t *pool = w->pool;
     int size = 1;
     pool[0].dist = oracle_l2sq_f32(q, base + (int64_t)start * d, d);
@@ -271,8 +267,7 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
         }
         size += add;
         qsort(pool, (size_t)size, sizeof(pent_t), pent_cmp);
-        int cap = (trunc_hop >= 0 && hops >= trunc_hop) ? trunc_L : L;
-        if (size > cap) size = cap;
+        if (size > L) size = L;
     }
     if (hops_out) *hops_out = hops;
     if (ndist_out) *ndist_out = ndist;
@@ -285,8 +280,8 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
  * out_dist are [nq][k_stride]; entries past k_i are left untouched; result
  * slots past the pool size hold (SENT, +inf).  hops/ndist may be NULL.
  * pool_ids/pool_dist ([nq][pool_stride], optional) receive the final pool.
- * trunc_hop/trunc_L_arr implement the learned early stop (see search_core);
- * pass trunc_hop < 0 to disable.
+ * max_hops_arr (optional): per-query expansion budget (the learned early
+ * stop); a query stops after that many expansions; values <= 0: no budget.
  * threads <= 0 uses the OpenMP default.
  */
 int oracle_search_batch(const float *base, int64_t n, int d,
@@ -296,13 +291,11 @@ int oracle_search_batch(const float *base, int64_t n, int d,
                         int k_stride, uint32_t *out_ids, float *out_dist,
                         int64_t *hops, int64_t *ndist,
                         uint32_t *pool_ids, float *pool_dist, int pool_stride,
-                        int64_t trunc_hop, const int32_t *trunc_L_arr,
-                        int threads)
+                        const int32_t *max_hops_arr, int threads)
 {
     if (n < 1 || d < 1 || R < 1 || start >= (uint64_t)n || nq < 0) return -1;
     int maxL = L;
     if (L_arr) { maxL = 1; for (int64_t i = 0; i < nq; ++i) if (L_arr[i] > maxL) maxL = L_arr[i]; }
-    if (trunc_L_arr) for (int64_t i = 0; i < nq; ++i) if (trunc_L_arr[i] > maxL) maxL = trunc_L_arr[i];
     int bad = 0;
     int nth = threads > 0 ? threads : omp_get_max_threads();
 #pragma omp parallel num_threads(nth)
@@ -314,11 +307,10 @@ int oracle_search_batch(const float *base, int64_t n, int d,
             if (bad) continue;
             int kk = k_arr ? k_arr[qi] : k;
             int LL = L_arr ? L_arr[qi] : L;
-            int tL = trunc_L_arr ? trunc_L_arr[qi] : LL;
+            int64_t budget = (max_hops_arr && max_hops_arr[qi] > 0) ? max_hops_arr[qi] : -1;
             int64_t h = 0, nd = 0;
             int size = search_core(base, d, graph, R, start, queries + qi * (int64_t)d,
-                                   LL, &w, &h, &nd, 0, -1,
-                                   trunc_L_arr ? trunc_hop : -1, tL, NULL, 0);
+                                   LL, &w, &h, &nd, 0, budget, NULL, 0);
             for (int j = 0; j < kk; ++j) {
                 out_ids[qi * k_stride + j] = j < size ? w.pool[j].id : SENT;
                 out_dist[qi * k_stride + j] = j < size ? w.pool[j].dist : INFINITY;
@@ -355,7 +347,7 @@ int oracle_search_one(const float *base, int64_t n, int d,
     if (ws_init(&w, n, L + R) != 0) { ws_free(&w); return -2; }
     int64_t h = 0, nd = 0;
     int size = search_core(base, d, graph, R, start, q, L, &w, &h, &nd, 1,
-                           stop_hop, -1, L, trace, trace_cap);
+                           stop_hop, trace, trace_cap);
     for (int j = 0; j < size; ++j) {
         if (pool_ids) pool_ids[j] = w.pool[j].id;
         if (pool_dist) pool_dist[j] = w.pool[j].dist;
@@ -401,7 +393,7 @@ int oracle_navigating_node(const float *base, int64_t n, int d,
     oracle_centroid(base, n, d, c);
     ws_t w;
     if (ws_init(&w, n, Lb + K) != 0) { ws_free(&w); free(c); return -2; }
-    search_core(base, d, knn, K, rand_start, c, Lb, &w, NULL, NULL, 0, -1, -1, Lb, NULL, 0);
+    search_core(base, d, knn, K, rand_start, c, Lb, &w, NULL, NULL, 0, -1, NULL, 0);
     *nav = w.pool[0].id;
     ws_free(&w);
     free(c);
@@ -453,7 +445,7 @@ static int collect_select(const float *base, int64_t n, int d,
                           int C, int m, uint32_t v, ws_t *w, uint32_t *row)
 {
     const float *qv = base + (int64_t)v * d;
-    search_core(base, d, knn, K, nav, qv, Lb, w, NULL, NULL, 1, -1, -1, Lb, NULL, 0);
+    search_core(base, d, knn, K, nav, qv, Lb, w, NULL, NULL, 1, -1, NULL, 0);
     /* the visited stamp marks exactly the visited ids; add unvisited kNN ids */
     for (int j = 0; j < K; ++j) {
         uint32_t u = knn[(int64_t)v * K + j];
@@ -541,7 +533,7 @@ int oracle_repair(const float *base, int64_t n, int d, uint32_t *graph, int m,
         uint32_t u = (uint32_t)scan;
         const float *qu = base + (int64_t)u * d;
         int size = search_core(base, d, graph, m, nav, qu, Lb, &w, NULL, NULL, 0,
-                               -1, -1, Lb, NULL, 0);
+                               -1, NULL, 0);
         int64_t wsel = -1;
         for (int t = 0; t < size; ++t) {
             uint32_t c = w.pool[t].id;

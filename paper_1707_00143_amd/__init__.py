@@ -42,7 +42,7 @@ class SearchOpts(ctypes.Structure):
         ("rerank", ctypes.c_int32),
         ("hops", ctypes.c_void_p),
         ("ndist", ctypes.c_void_p),
-        ("L_used", ctypes.c_void_p),
+        ("budget", ctypes.c_void_p),
         ("features", ctypes.c_void_p),
         ("pool_ids", ctypes.c_void_p),
         ("pool_dist", ctypes.c_void_p),
@@ -51,6 +51,7 @@ class SearchOpts(ctypes.Structure):
         ("nedges", ctypes.c_void_p),
         ("lanes_per_row", ctypes.c_int32),
         ("counter", ctypes.c_void_p),
+        ("max_hops", ctypes.c_int32),
     ]
 
 
@@ -283,7 +284,10 @@ def recall_hits(found, truth, k, stream=None):
 def _opts(opts):
     o = SearchOpts()
     keep = []
+    names = {f[0] for f in SearchOpts._fields_}
     for key, val in (opts or {}).items():
+        if key not in names:
+            raise KeyError(f"unknown search option {key!r}")
         if isinstance(val, torch.Tensor):
             if not val.is_cuda or not val.is_contiguous():
                 raise ValueError(f"opts[{key}] must be a contiguous CUDA tensor")

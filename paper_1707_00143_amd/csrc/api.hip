@@ -256,7 +256,6 @@ static int check_search_common(const nsg_index *idx, const float *queries, int64
 
 static int stop_ready(const nsg_index *idx) { return idx->stop.enabled && idx->stop.f32 && idx->stop.grid; }
 
-static int stop_cap(const nsg_index *idx) { return std::max(16, idx->stop.grid_max); }
 
 extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
                           uint32_t *out_ids, float *out_dist, void *stream) {
@@ -276,8 +275,8 @@ extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq
     a.out_ids = out_ids;
     a.out_dist = out_dist;
     a.learned = stop_ready(idx) && L >= 16;
-    a.L_cap = a.learned ? std::max(L, stop_cap(idx)) : L;
-    a.hash_bits = default_hash_bits(a.learned ? std::max(L, 64) : a.L_cap);
+    a.L_cap = L;
+    a.hash_bits = default_hash_bits(L);
     a.rerank = idx->storage != NSG_F32;
     // large batches: persistent grid (work stealing evens out per-query cost)
     a.persistent = nq >= kPersistentMinBatch;
@@ -309,6 +308,7 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     if (o.pool_ids && (o.pool_stride < 1 || !o.pool_dist)) return fail(NSG_EINVAL, "pool output needs stride and dist");
     if (o.learned_stop && !stop_ready(idx)) return fail(NSG_ESTATE, "no early-stop model loaded and enabled");
     if (o.feature_hop < 0) return fail(NSG_EINVAL, "feature_hop < 0");
+    if (o.max_hops < 0) return fail(NSG_EINVAL, "max_hops < 0");
     if (o.lanes_per_row && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
         o.lanes_per_row != 64)
         return fail(NSG_EINVAL, "lanes_per_row must be 0, 8, 16, 32 or 64");
@@ -326,9 +326,8 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.out_ids = out_ids;
     a.out_dist = out_dist;
     a.learned = o.learned_stop ? 1 : 0;
-    a.L_cap = a.learned ? std::max((int)L_scalar, stop_cap(idx)) : L_scalar;
-    // learned: most queries stop near the fallback L; size the filter for it
-    int hb = default_hash_bits(a.learned ? std::max((int)L_scalar, 64) : a.L_cap);
+    a.L_cap = L_scalar;
+    int hb = default_hash_bits(a.L_cap);
     if (o.hash_slots) { hb = 0; while ((1 << hb) < o.hash_slots) ++hb; }
     a.hash_bits = hb;
     a.waves_per_block = o.waves_per_block;
@@ -337,7 +336,8 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.rerank = o.rerank == 0 ? (idx->storage != NSG_F32) : (o.rerank > 0);
     a.hops = o.hops;
     a.ndist = o.ndist;
-    a.L_used = o.L_used;
+    a.budget = o.budget;
+    a.max_hops = o.max_hops;
     a.features = o.features;
     a.feature_hop = o.feature_hop;
     a.nedges = o.nedges;
@@ -369,7 +369,7 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
     const float *mean = b, *istd = b + in, *W1 = istd + in, *b1 = W1 + (size_t)h * in, *W2 = b1 + h;
     const float *b2 = W2 + (size_t)h * h, *W3 = b2 + h, *b3 = W3 + h, *grid = b3 + 1;
     for (int i = 0; i < grid_n; ++i) {
-        if (!(grid[i] >= 1.0f && grid[i] <= (float)kMaxL)) return fail(NSG_EINVAL, "grid value out of [1, 512]");
+        if (!(grid[i] >= 1.0f && grid[i] <= 1048576.0f)) return fail(NSG_EINVAL, "grid value out of [1, 2^20]");
         if (i && grid[i] <= grid[i - 1]) return fail(NSG_EINVAL, "grid must be strictly ascending");
     }
     std::vector<float> f32;
@@ -399,7 +399,6 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
     sm.h = h;
     sm.hop = hop;
     sm.grid_n = grid_n;
-    sm.grid_max = (int)grid[grid_n - 1];
     sm.enabled = idx->stop.enabled;
     sm.calib_c = idx->stop.calib_c;
     hipDeviceSynchronize();

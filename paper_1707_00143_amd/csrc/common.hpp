@@ -33,7 +33,7 @@ struct StopModel {
     float *f32 = nullptr;      // device: mean[in], inv_std[in], b1[h], b2[h], b3
     void *w16 = nullptr;       // device FP16: W1T[in][h], W2T[h][h], W3[h]
     float *grid = nullptr;     // device: grid values (ascending)
-    int in = 0, h = 0, hop = 0, grid_n = 0, grid_max = 16;
+    int in = 0, h = 0, hop = 0, grid_n = 0;
     int enabled = 0;
     float calib_c = 1.0f;
 };
@@ -85,7 +85,8 @@ struct SearchArgs {
     int32_t feature_hop;      // decision / trace hop (0: 16)
     int32_t lanes_per_row;    // 0: default layout
     unsigned int *counter;    // persistent work counter (NULL: allocated per call)
-    int32_t *L_used;
+    int32_t *budget;
+    int32_t max_hops;
     float *features;
     uint32_t *pool_ids;
     float *pool_dist;

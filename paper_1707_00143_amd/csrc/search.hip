@@ -66,7 +66,8 @@ int launch_search(const SearchArgs &a) {
     p.hops = a.hops;
     p.ndist = a.ndist;
     p.nedges = a.nedges;
-    p.L_used = a.L_used;
+    p.budget = a.budget;
+    p.max_hops = a.max_hops;
     p.features = a.features;
     p.pool_ids = a.pool_ids;
     p.pool_dist = a.pool_dist;
@@ -119,7 +120,7 @@ int launch_search(const SearchArgs &a) {
     }
     const bool full = a.features || a.vis_ids || a.pool_ids || a.hops || a.ndist || a.nedges ||
                       a.self_offset >= 0;
-    const int mode = full ? 2 : (a.learned || a.L_used) ? 1 : 0;
+    const int mode = full ? 2 : (a.learned || a.budget) ? 1 : 0;
     const int nch = L_alloc <= 128 ? 2 : L_alloc <= 256 ? 4 : 8;   // pool registers per lane: 2 * nch
     kfn_t fn = nullptr;
     switch (ix->storage) {

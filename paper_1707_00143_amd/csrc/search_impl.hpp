@@ -24,7 +24,8 @@ struct KParams {
     int rerank;
     unsigned int *counter;
     int64_t *hops, *ndist, *nedges;
-    int32_t *L_used;
+    int32_t *budget;             // chosen expansion budget per query (learned stop), or NULL
+    int max_hops;                // expansion budget for every query (0: none)
     float *features;
     uint32_t *pool_ids;
     float *pool_dist;
@@ -136,7 +137,7 @@ __device__ inline void stop_features(const KParams &p, const float *q, float d0,
 
 // learned early stop: z-scored features in xbuf -> MLP (FP16 weights, FP32
 // accumulate) -> y = log2 pool size -> L_hat on the grid
-__device__ inline int stop_predict(const KParams &p, int Lq, int kq, const float *xbuf, int lane) {
+__device__ inline int stop_predict(const KParams &p, const float *xbuf, int lane) {
     const int in = p.s_in, h = p.s_h;
     // the model is the same for every query: opaque base pointers keep the
     // compiler from hoisting its loads out of the search loop (they would
@@ -171,19 +172,16 @@ __device__ inline int stop_predict(const KParams &p, int Lq, int kq, const float
     for (int off = 32; off > 0; off >>= 1) o += __shfl_xor(o, off);
     o += b3;
     wave_sync();
-    if (!isfinite(o)) return Lq;
+    if (!isfinite(o)) return 0x7FFFFFFF;   // no budget: the plain search
     float t = p.calib_c * exp2f(o);
-    int pick = p.grid_n > 0 ? (int)p.grid[p.grid_n - 1] : kMaxL;
+    int pick = p.grid_n > 0 ? (int)p.grid[p.grid_n - 1] : 0x7FFFFFFF;
     for (int b = 0; b < p.grid_n; b += 64) {
         int i = b + lane;
         bool ge = i < p.grid_n && p.grid[i] >= t;
         uint64_t bm = __ballot(ge);
         if (bm) { pick = (int)p.grid[b + __ffsll((long long)bm) - 1]; break; }
     }
-    int lo = kq > 16 ? kq : 16;
-    if (pick < lo) pick = lo;
-    if (pick > p.L_cap) pick = p.L_cap;
-    return pick;
+    return pick < p.s_hop ? p.s_hop : pick;
 }
 
 // MODE selects what is compiled in: 0 the plain search only; 1 also the
@@ -223,7 +221,11 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
         int Lq = p.L_arr ? p.L_arr[qi] : p.L_scalar;
         Lq = Lq < 1 ? 1 : (Lq > p.L_cap ? p.L_cap : Lq);
         const bool learned = LEARN && p.learned && Lq >= 16;
-        int Lcur = learned ? p.L_cap : Lq;
+        const int Lcur = Lq;
+        // expansion budget: the caller's, and after the decision hop the
+        // learned one (the search stops early, never later, than plain)
+        int64_t hcap = p.max_hops > 0 ? p.max_hops : INT64_MAX;
+        int chosen = 0;
 
         // query chunks in registers, aligned with the row chunks this lane reads
         float qv[CPL][EPC], sc[CPL][EPC];
@@ -265,6 +267,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
         rp_insert<NCH>(P, readfirstlane64(mk_key(cdist[0], start)), Lcur, lane);
         bool stopped = !learned && !(FULL && p.features);   // true once the decision hop has passed
         for (;;) {
+            if (hops >= hcap) break;
             // Algorithm 1: expand the first unchecked pool entry
             uint64_t pe;
             const int i = rp_first_unchecked<NCH>(P, &pe);
@@ -309,19 +312,14 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
                 const float d9 = key_dist(rp_get<NCH>(P, P.size > 10 ? 9 : P.size - 1));
                 stop_features<FULL>(p, q, d0, d9, hops, xbuf, lane, qi);
                 if (learned) {
-                    Lcur = stop_predict(p, Lq, kq, xbuf, lane);
-                    rp_truncate<NCH>(P, Lcur, lane);
+                    chosen = stop_predict(p, xbuf, lane);
+                    hcap = chosen < hcap ? chosen : hcap;
                 }
             }
         }
-        if (LEARN && !stopped) {
-            // ended before the decision point: the result equals the plain one
-            if (FULL && p.features)
-                for (int t = lane; t < p.d + 3; t += 64) p.features[qi * (int64_t)(p.d + 3) + t] = NAN;
-            if (learned) {
-                Lcur = Lq;
-                rp_truncate<NCH>(P, Lcur, lane);
-            }
+        if (FULL && !stopped && p.features) {
+            // ended before the decision point: no features (the result is the plain one)
+            for (int t = lane; t < p.d + 3; t += 64) p.features[qi * (int64_t)(p.d + 3) + t] = NAN;
         }
         rp_store<NCH>(P, pool, lane);
         const int size = P.size;
@@ -376,7 +374,7 @@ __global__ void __launch_bounds__(256) search_kernel(KParams p) {
             if (p.nedges) p.nedges[qi] = ne;
             if (p.vis_cnt) p.vis_cnt[qi] = vcount;
         }
-        if (LEARN && lane == 0 && p.L_used) p.L_used[qi] = Lcur;
+        if (LEARN && lane == 0 && p.budget) p.budget[qi] = chosen;
         wave_sync();
         if (!p.counter) break;
         unsigned int t = 0;

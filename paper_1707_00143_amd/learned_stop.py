@@ -1,16 +1,18 @@
 """Learned early termination: traces, labels, training and calibration.
 
 Driver around the library's kernels (an extension of the method; the paper
-has no early stop).  For every training query the plain search is run at each
-pool size of a geometric grid (16 .. 512 in 2^(1/4) steps); the label is
-log2 of the smallest grid L whose top-k equals the exact top-k (queries that
-never reach it are censored at 512).  Features are taken after the 16th
-expansion, where every run with L >= 16 has made the same expansions, so one
+has no early stop).  The search keeps its pool size L and gets a per-query
+expansion budget.  For every training query the plain search is run with a
+budget at each value of a geometric grid (16 .. 1024 expansions in 2^(1/4)
+steps); the label is log2 of the smallest budget whose top-k equals the top-k
+of the unbudgeted plain search (the plain search is the judge: the label is
+where the search has converged to its own answer, finite for every query).
+Features are taken after the 16th expansion, the same in every run, so one
 capture serves every grid point.  The network (d+3 -> 64 -> 64 -> 1, ReLU) is
 trained with the library's forward/backward and Adam kernels on z-scored
 features; the calibration constant c is the smallest one whose held-out mean
-recall meets the target when the pool is cut to the grid value at or above
-c * 2^y.
+recall meets the target when each query's budget is the grid value at or
+above c * 2^y.
 """
 from __future__ import annotations
 
@@ -22,7 +24,7 @@ import torch
 from . import (column_stats, load_stop_model, mlp_adam, mlp_forward, mlp_forward_backward, recall_hits,
                search_batched, set_stop_mode)
 
-GRID = [int(round(16 * 2 ** (i / 4))) for i in range(21)]   # 16, 19, 23, ..., 512
+GRID = [int(round(16 * 2 ** (i / 4))) for i in range(25)]   # 16, 19, 23, ..., 1024 expansions
 HOP = 16
 HIDDEN = 64
 
@@ -30,37 +32,47 @@ HIDDEN = 64
 @dataclasses.dataclass
 class Traces:
     features: torch.Tensor   # [nq][d+3] float32 (NaN rows: search ended before the hop)
-    hits: torch.Tensor       # [nq][G] int32: |top-k at grid L ∩ exact top-k|
+    hits: torch.Tensor       # [nq][G] int32: |top-k within budget grid[j] ∩ exact top-k|
     grid: list
+    hops: torch.Tensor = None   # [nq] int64: expansions of the unbudgeted search
+    same: torch.Tensor = None   # [nq][G] int32: |top-k within budget grid[j] ∩ unbudgeted top-k|
 
 
-def traces(index, queries, truth, k=10, grid=GRID, chunk=50_000):
-    """Plain search at every grid L; features at HOP from the first run."""
+def traces(index, queries, truth, L, k=10, grid=GRID, chunk=50_000):
+    """Plain search at pool size L under every grid budget; features at HOP."""
     nq, d = queries.shape
     dev = queries.device
     feats = torch.empty((nq, d + 3), dtype=torch.float32, device=dev)
     hits = torch.empty((nq, len(grid)), dtype=torch.int32, device=dev)
+    hops = torch.empty(nq, dtype=torch.int64, device=dev)
+    same = torch.empty((nq, len(grid)), dtype=torch.int32, device=dev)
     found = torch.empty((min(chunk, nq), len(grid), k), dtype=torch.int32, device=dev)
     for s in range(0, nq, chunk):
         e = min(nq, s + chunk)
         q = queries[s:e]
-        for g, L in enumerate(grid):
+        for g, B in enumerate(grid):
             ids = torch.empty((e - s, k), dtype=torch.int32, device=dev)
             dist = torch.empty((e - s, k), dtype=torch.float32, device=dev)
-            opts = dict(features=feats[s:e], feature_hop=HOP) if g == 0 else None
+            opts = dict(max_hops=B)
+            if g == 0:
+                opts.update(features=feats[s:e], feature_hop=HOP)
             search_batched(index, q, k_scalar=k, L_scalar=L, out_ids=ids, out_dist=dist, opts=opts)
             found[:e - s, g].copy_(ids)
+        final, _ = search_batched(index, q, k_scalar=k, L_scalar=L, opts=dict(hops=hops[s:e]))
         hits[s:e] = recall_hits(found[:e - s].contiguous(), truth[s:e].contiguous(), k)
-    return Traces(feats, hits, list(grid))
+        same[s:e] = recall_hits(found[:e - s].contiguous(), final.contiguous(), k)
+    return Traces(feats, hits, list(grid), hops, same)
 
 
 def labels(tr: Traces, k=10):
-    """y = log2 of the smallest grid L reaching the exact top-k (censored at the top)."""
-    h = tr.hits.cpu().numpy()
+    """y = log2 of the smallest grid budget whose top-k is the unbudgeted
+    search's (censored at the top of the grid if none is); also returns
+    which queries reach it."""
+    h = tr.same.cpu().numpy()
     ok = h >= k
     first = np.where(ok.any(1), ok.argmax(1), len(tr.grid) - 1)
-    L = np.asarray(tr.grid)[first]
-    return np.log2(L).astype(np.float32), ok.any(1)
+    B = np.asarray(tr.grid)[first]
+    return np.log2(B).astype(np.float32), ok.any(1)
 
 
 def init_params(n_in, h, seed):
@@ -123,33 +135,33 @@ def predict(P, mean, istd, features):
     return mlp_forward(P, Xz.shape[1], HIDDEN, Xz)
 
 
-def l_hat(yhat, c, grid, k=10):
-    """Pool size the kernel picks: smallest grid value >= c * 2^y, clamped."""
+def budget(yhat, c, grid, hop=HOP):
+    """Expansion budget the kernel picks: smallest grid value >= c * 2^y (the
+    largest if none is), at least the decision hop; NaN for a non-finite y."""
     t = c * np.exp2(np.asarray(yhat, np.float64))
     g = np.asarray(grid, np.float64)
     idx = np.searchsorted(g, t, side="left")
     idx = np.clip(idx, 0, len(g) - 1)
-    L = g[idx]
-    L = np.maximum(L, max(16, k))
-    return np.where(np.isfinite(t), L, np.nan)
+    B = np.maximum(g[idx], hop)
+    return np.where(np.isfinite(t), B, np.nan)
 
 
-def calibrate(yhat, hits, grid, k=10, target=0.95, margin=0.0):
-    """Smallest c (on a 2^(1/16) ladder) whose mean held-out recall >= target."""
+def calibrate(yhat, hits, grid, k=10, target=0.95, margin=0.0, hops=None):
+    """Smallest c (on a 2^(1/16) ladder) whose mean held-out recall >= target.
+    Returns (c, recall, mean budget, mean expansions) (the last needs `hops`,
+    the unbudgeted expansion counts), or None."""
     yhat = np.asarray(yhat)
     h = np.asarray(hits)
     g = np.asarray(grid)
-    best = None
-    for j in range(-64, 97):
+    for j in range(-64, 129):
         c = 2.0 ** (j / 16)
-        L = l_hat(yhat, c, grid, k)
-        col = np.searchsorted(g, L)
-        col = np.clip(col, 0, len(g) - 1)
+        B = budget(yhat, c, grid)
+        col = np.clip(np.searchsorted(g, B), 0, len(g) - 1)
         rec = h[np.arange(len(h)), col] / k
         if rec.mean() >= target + margin:
-            best = (c, float(rec.mean()), float(L.mean()))
-            break
-    return best
+            used = float(np.minimum(B, hops).mean()) if hops is not None else float("nan")
+            return c, float(rec.mean()), float(B.mean()), used
+    return None
 
 
 def model_blob(P, mean, istd, grid):

@@ -122,11 +122,11 @@ def _random_model(nsg, ix, Qd, seed):
     return Pd, mean, istd
 
 
-def test_learned_stop_equals_plain_at_chosen_L(nsg, tiny_index):
+def test_learned_stop_equals_plain_with_chosen_budget(nsg, tiny_index):
     """With the early stop on, each query's output equals the plain search
-    at the pool size the network picked (on the GPU and in the oracle, which
-    cuts an L=512 run to L_hat after 16 expansions); features match the
-    oracle's pool after 16 expansions; the fallback is bit-identical to plain."""
+    stopped after the expansion budget the network picked (on the GPU, and in
+    the oracle's Algorithm 1 with that budget); features match the oracle's
+    pool after 16 expansions; the fallback is bit-identical to plain."""
     dev = _dev()
     from paper_1707_00143_amd import learned_stop as ls
     X, G, nav, Q = tiny_index["X"], tiny_index["graph"], tiny_index["nav"], tiny_index["Q"]
@@ -134,28 +134,35 @@ def test_learned_stop_equals_plain_at_chosen_L(nsg, tiny_index):
     Qd = torch.from_numpy(Q).to(dev)
     nq, k, L = len(Q), 10, 60
     plain = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L)
+    hops_plain = torch.zeros(nq, dtype=torch.int64, device=dev)
+    nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(hops=hops_plain))
     P, mean, istd = _random_model(nsg, ix, Qd, 5)
     ls.install(ix, P, mean, istd, 1.0)
-    Lu = torch.empty(nq, dtype=torch.int32, device=dev)
+    Bu = torch.empty(nq, dtype=torch.int32, device=dev)
     feats = torch.empty((nq, X.shape[1] + 3), dtype=torch.float32, device=dev)
+    hops = torch.zeros(nq, dtype=torch.int64, device=dev)
     ids, dist = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L,
-                                   opts=dict(learned_stop=1, L_used=Lu, features=feats))
-    Lu = _np(Lu)
-    assert len(set(Lu.tolist())) > 3, Lu                     # the model spreads its picks
-    assert set(Lu.tolist()) <= set(ls.GRID)
-    # GPU: equal to plain search at the chosen pool size
-    for Lv in sorted(set(Lu.tolist())):
-        sel = np.where(Lu == Lv)[0]
-        pi, pdist = nsg.search(ix, Qd[torch.from_numpy(sel).to(dev)].contiguous(), k, int(Lv))
+                                   opts=dict(learned_stop=1, budget=Bu, features=feats, hops=hops))
+    Bu, hops, hp = _np(Bu), _np(hops), _np(hops_plain)
+    assert len(set(Bu.tolist())) > 3, Bu                     # the model spreads its picks
+    assert set(Bu.tolist()) <= set(ls.GRID)
+    assert (hops == np.minimum(Bu, hp)).all()                 # stops at the budget or earlier
+    assert (hops < hp).any() and (hops == hp).any()           # some cut, some not
+    # GPU: equal to the plain search with that budget
+    for B in sorted(set(Bu.tolist())):
+        sel = np.where(Bu == B)[0]
+        pi, pdist = nsg.search_batched(ix, Qd[torch.from_numpy(sel).to(dev)].contiguous(), k_scalar=k,
+                                       L_scalar=L, opts=dict(max_hops=int(B)))
         assert (_np(pi) == _np(ids)[sel]).all() and (_np(pdist) == _np(dist)[sel]).all()
-    # oracle: L=512 cut to L_hat after 16 expansions
-    o_ids, _, _, _ = oracle.search(X, G, nav, Q, k, 512, trunc_hop=16, trunc_L=Lu)
+    # oracle: Algorithm 1 with the per-query budget
+    o_ids, _, o_hops, _ = oracle.search(X, G, nav, Q, k, L, max_hops=Bu)
+    assert (o_hops == hops).all()
     r = compare(X, Q, _np(ids).view(np.uint32), _np(dist), o_ids)
     assert r["ok"], r
     # features after 16 expansions
     f = _np(feats)
     for i in range(0, nq, 10):
-        one = oracle.search_one(X, G, nav, Q[i], 512, stop_hop=16)
+        one = oracle.search_one(X, G, nav, Q[i], L, stop_hop=16)
         d0, d9 = one["pool_dist"][0], one["pool_dist"][9]
         np.testing.assert_allclose(f[i, :128], Q[i])
         np.testing.assert_allclose(f[i, 128], d0, rtol=1e-5)
@@ -164,11 +171,28 @@ def test_learned_stop_equals_plain_at_chosen_L(nsg, tiny_index):
     # the network's pick: the grid value at or above c * 2^y (FP16 weights, so
     # allow picks that straddle a grid boundary within 1 %)
     yo = _np(ls.predict(P, mean, istd, feats))
-    lo = ls.l_hat(yo - np.log2(1.01), 1.0, ls.GRID, k)
-    hi = ls.l_hat(yo + np.log2(1.01), 1.0, ls.GRID, k)
-    assert ((Lu >= lo) & (Lu <= hi)).all()
+    lo = ls.budget(yo - np.log2(1.01), 1.0, ls.GRID)
+    hi = ls.budget(yo + np.log2(1.01), 1.0, ls.GRID)
+    assert ((Bu >= lo) & (Bu <= hi)).all()
     # fallback: disabled model -> bit-identical to plain
     nsg.set_stop_mode(ix, False, 1.0)
     fb = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L)
     assert (fb[0] == plain[0]).all() and (fb[1] == plain[1]).all()
+    ix.close()
+
+
+def test_max_hops_matches_oracle(nsg, tiny_index):
+    """A caller-given expansion budget equals the oracle's Algorithm 1 stopped
+    after that many expansions (FP32, several budgets in one batch)."""
+    dev = _dev()
+    X, G, nav, Q = tiny_index["X"], tiny_index["graph"], tiny_index["nav"], tiny_index["Q"]
+    ix = nsg.load_index(torch.from_numpy(X).to(dev), torch.from_numpy(G.view(np.int32)).to(dev), nav, "f32")
+    Qd = torch.from_numpy(Q).to(dev)
+    for B in (1, 7, 16, 33, 1000):
+        hops = torch.zeros(len(Q), dtype=torch.int64, device=dev)
+        ids, dist = nsg.search_batched(ix, Qd, k_scalar=10, L_scalar=50, opts=dict(max_hops=B, hops=hops))
+        o_ids, _, o_hops, _ = oracle.search(X, G, nav, Q, 10, 50, max_hops=B)
+        assert (_np(hops) == o_hops).all(), B
+        r = compare(X, Q, _np(ids).view(np.uint32), _np(dist), o_ids)
+        assert r["ok"], (B, r)
     ix.close()

@@ -111,16 +111,42 @@ def test_pool_invariant_and_warmup_invariance(tiny_index):
         assert all((t == traces[0]).all() for t in traces)
 
 
-def test_truncation_equals_plain_search(tiny_index):
-    """Cutting an L=512 run to L_hat >= 16 after 16 expansions yields exactly the
-    plain L_hat search (pool invariant + warm-up invariance)."""
+def test_expansion_budget_is_a_prefix_of_the_plain_search(tiny_index):
+    """A budget of B expansions (the learned early stop) is the plain search
+    cut after its first B expansions: its pool is, by brute force, the L
+    smallest (distance, id) keys over the start and the neighbours of the
+    first B nodes of the unbounded run's expansion trace; its hop count is
+    min(B, the unbounded count)."""
     X, G, nav, Q = tiny_index["X"], tiny_index["graph"], tiny_index["nav"], tiny_index["Q"]
-    Lhat = np.array([16, 23, 64, 100, 512] * 4, np.int32)
-    q = Q[:20]
-    ids_t, d_t, h_t, nd_t = oracle.search(X, G, nav, q, 10, 512, trunc_hop=16, trunc_L=Lhat)
-    for i in range(20):
-        ids_p, d_p, h_p, nd_p = oracle.search(X, G, nav, q[i:i + 1], 10, int(Lhat[i]))
-        assert (ids_t[i] == ids_p[0]).all() and h_t[i] == h_p[0] and nd_t[i] == nd_p[0]
+    L, k = 40, 10
+    budgets = np.array([1, 2, 5, 16, 17, 30, 60, 10_000] * 2, np.int32)
+    q = Q[:len(budgets)]
+    ids_b, d_b, h_b, _, pids, pd = oracle.search(X, G, nav, q, k, L, pool_stride=L, max_hops=budgets)
+    for i in range(len(budgets)):
+        full = oracle.search_one(X, G, nav, q[i], L)
+        H = int(full["hops"])
+        B = min(int(budgets[i]), H)
+        assert h_b[i] == B
+        seen = {int(nav)}
+        for v in full["trace"][:B]:
+            seen.update(int(u) for u in G[v] if u != SENT)
+        ids = np.fromiter(seen, np.int64)
+        dd = ((X[ids].astype(np.float64) - q[i].astype(np.float64)) ** 2).sum(1)
+        order = np.lexsort((ids, dd))[:L]
+        want = ids[order]
+        got = pids[i][pids[i] != SENT].astype(np.int64)
+        # compared as sets; FP32 and FP64 may only disagree on keys within
+        # 1e-5 (relative) of the L-th distance
+        dL = dd[order[-1]]
+        diff = set(got.tolist()) ^ set(want.tolist())
+        dmap = dict(zip(ids.tolist(), dd.tolist()))
+        assert all(abs(dmap[u] - dL) <= 1e-5 * dL for u in diff), (i, diff)
+        assert len(got) == len(want)
+        assert np.all(np.diff(pd[i][:len(got)]) >= 0)
+    # no budget (or one above the natural count) equals the plain search
+    ids_p, _, h_p, _ = oracle.search(X, G, nav, q, k, L)
+    big = budgets >= 10_000
+    assert (ids_b[big] == ids_p[big]).all() and (h_b[big] == h_p[big]).all()
 
 
 def test_per_query_k_and_L(tiny_index):
