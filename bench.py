@@ -33,6 +33,33 @@ sys.path.insert(0, ROOT)
 T0 = time.time()
 
 
+def source_sha256():
+    """Hash of the library sources (kernels, host code, ABI header)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1707_00143_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")))
+    for f in files + [os.path.join(ROOT, "include", "nsg.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the plain FP32 search from the committed
+    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known
+    size), or None if the library sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "search_f32_sift1m_like_traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return int(t["traffic_bytes"]) if t.get("src_sha256") == source_sha256() else None
+
+
 def log(msg):
     print(f"[bench {time.time() - T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
@@ -309,8 +336,9 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
     alg_bytes = N * d * 4 + (E + H) * 4 + nq * (d * 4 + k * 8)
     achieved = alg_bytes / (ms32 / 1e3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=8000.0, unit="GB/s",
-                frac=round(achieved / 8000.0, 4), traffic=None,
-                kernel="search_kernel<F32,8,4>", bytes_per_launch=int(alg_bytes),
+                frac=round(achieved / 8000.0, 4), traffic=measured_traffic(),
+                kernel="search_kernel<F32, lanes per row 8, chunks per lane 4, plain, 2 pool chunks>",
+                bytes_per_launch=int(alg_bytes),
                 per_query=dict(hops=H / nq, ndist=N / nq, edges=E / nq))
     log(f"roofline: {roof}")
 
