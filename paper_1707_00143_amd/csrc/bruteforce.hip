@@ -6,9 +6,12 @@
 // v_mfma_f32_16x16x4f32 (each of the 4 waves: 16 queries x 64 rows), turned
 // into approximate squared distances |q-mu|^2 + |x-mu|^2 - 2 (q-mu).(x-mu),
 // and every value below the query's current threshold is appended to that
-// query's LDS buffer.  A buffer that passes Kp entries is sorted and cut back
-// to its Kp best, which tightens the threshold.  Each block writes Kp
-// candidates per query for its split.
+// query's LDS buffer.  A buffer that could overflow on the next tile is
+// sorted and cut back to its Kp best, which tightens the threshold (the
+// buffer holds Kp + 2 tiles, so sorts are rare once the threshold is tight).
+// With d <= 128 each wave keeps its 16 centred queries as matrix-core
+// operands in registers for the whole scan and only base rows are staged.
+// Each block writes Kp candidates per query for its split.
 // Stage 2: per query (one wave), exact FP32 squared distances sum (q_j-x_j)^2
 // of all candidates of all splits, bitonic sort by (distance, id), first k.
 // Centring keeps the cancellation error of the inner-product form small;
@@ -99,6 +102,7 @@ __device__ inline void wave_sort_buf(uint64_t *buf, int cnt, int cap, int lane) 
         }
 }
 
+template <bool AREG>
 __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     float *Qs = reinterpret_cast<float *>(smem);             // [KB][KPAD]
@@ -114,33 +118,82 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
     if (tid < BQ) { thr[tid] = INFINITY; cnt[tid] = 0; }
     bsync();
     const int rq = lane & 15, kq = lane >> 4;   // MFMA operand row / k group of this lane
+    // centred query operands of this wave (AREG: d <= 128, k-step s uses a[s])
+    float a_reg[AREG ? 32 : 1];
+    if (AREG) {
+        const int64_t qi = q0 + 16 * w + rq;
+#pragma unroll
+        for (int s4 = 0; s4 < (AREG ? 32 : 1); ++s4) {
+            const int j = 4 * s4 + kq;
+            a_reg[s4] = (qi < p.nq && j < p.d) ? p.queries[qi * p.d + j] - p.mu[j] : 0.0f;
+        }
+    }
+    // |q - mu|^2 of the 4 query rows this lane's accumulators hold
+    float qn[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t qi = q0 + 16 * w + 4 * kq + i;
+        qn[i] = qi < p.nq ? p.qnorm[qi] : 0.0f;
+    }
+    // base chunk (64 rows x 32 dims) of the next step, loaded into registers
+    // while the matrix cores work on the current one (AREG path)
+    float xr[(BX * KB) / 256];
+    const int kk_t = tid % KB;   // the dimension offset this thread stages (fixed: 256 % KB == 0)
+    auto load_chunk = [&](int64_t cx0, int ck0) {
+#pragma unroll
+        for (int it = 0; it < (BX * KB) / 256; ++it) {
+            const int r = (tid + it * 256) / KB;
+            const int j = ck0 + kk_t;
+            const int64_t xi = cx0 + r;
+            xr[it] = (xi < xe && j < p.d) ? p.base[xi * p.d + j] : 0.0f;
+        }
+    };
+    if (AREG) load_chunk(xb, 0);
     for (int64_t x0 = xb; x0 < xe; x0 += BX) {
         f32x4 acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k0 = 0; k0 < p.d; k0 += KB) {
-            // stage centred Q and X chunks, k-major: 64 rows x 32 dims each
 #pragma unroll
-            for (int it = 0; it < (BQ * KB) / 256; ++it) {
-                int e = tid + it * 256;
-                int r = e / KB, kk = e % KB;
-                int j = k0 + kk;
-                int64_t qi = q0 + r, xi = x0 + r;
-                float mj = j < p.d ? p.mu[j] : 0.0f;
-                Qs[kk * KPAD + r] = (qi < p.nq && j < p.d) ? p.queries[qi * p.d + j] - mj : 0.0f;
-                Xs[kk * KPAD + r] = (xi < xe && j < p.d) ? p.base[xi * p.d + j] - mj : 0.0f;
+        for (int k0 = 0; k0 < (AREG ? 128 : 65536); k0 += KB) {
+            if (k0 >= p.d) break;   // AREG: a constant trip count keeps a_reg in registers
+            if (AREG) {
+                // stage the prefetched chunk, centred, k-major; then prefetch the next
+                bsync();
+                const int j = k0 + kk_t;
+                const float mj = j < p.d ? p.mu[j] : 0.0f;
+#pragma unroll
+                for (int it = 0; it < (BX * KB) / 256; ++it) {
+                    const int r = (tid + it * 256) / KB;
+                    Xs[kk_t * KPAD + r] = (x0 + r < xe && j < p.d) ? xr[it] - mj : 0.0f;
+                }
+                bsync();
+                const bool more_k = k0 + KB < p.d;
+                const int64_t nx0 = more_k ? x0 : x0 + BX;
+                if (nx0 < xe) load_chunk(nx0, more_k ? k0 + KB : 0);
+            } else {
+                // stage centred Q and X chunks, k-major: 64 rows x 32 dims each
+#pragma unroll
+                for (int it = 0; it < (BQ * KB) / 256; ++it) {
+                    int e = tid + it * 256;
+                    int r = e / KB, kk = e % KB;
+                    int j = k0 + kk;
+                    int64_t qi = q0 + r, xi = x0 + r;
+                    float mj = j < p.d ? p.mu[j] : 0.0f;
+                    Qs[kk * KPAD + r] = (qi < p.nq && j < p.d) ? p.queries[qi * p.d + j] - mj : 0.0f;
+                    Xs[kk * KPAD + r] = (xi < xe && j < p.d) ? p.base[xi * p.d + j] - mj : 0.0f;
+                }
+                bsync();
             }
-            bsync();
 #pragma unroll
             for (int kk = 0; kk < KB; kk += 4) {
-                float a = Qs[(kk + kq) * KPAD + 16 * w + rq];
+                float a = AREG ? a_reg[((k0 + kk) >> 2) & 31] : Qs[(kk + kq) * KPAD + 16 * w + rq];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     float b = Xs[(kk + kq) * KPAD + 16 * t + rq];
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
                 }
             }
-            bsync();
+            if (!AREG) bsync();
         }
         // epilogue: lane holds rows 4*kq + i of this wave's 16 queries, column rq of tile t
 #pragma unroll
@@ -151,7 +204,7 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
                 int r = 16 * w + 4 * kq + i;
                 int64_t qi = q0 + r;
                 if (xi < xe && qi < p.nq && !(p.exclude_self && xi == qi)) {
-                    float dd = p.qnorm[qi] + p.xnorm[xi] - 2.0f * acc[t][i];
+                    float dd = qn[i] + p.xnorm[xi] - 2.0f * acc[t][i];
                     dd = fmaxf(dd, 0.0f);
                     if (dd < thr[r]) {
                         int s = atomicAdd(&cnt[r], 1);
@@ -161,10 +214,10 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
             }
         }
         bsync();
-        // compaction: wave w handles queries w, w+4, ...
+        // compaction when the next tile could overflow: wave w handles queries w, w+4, ...
         for (int r = w; r < BQ; r += 4) {
             int c = cnt[r];
-            if (c > p.Kp) {
+            if (c > p.cap - BX) {
                 wave_sort_buf(buf + (size_t)r * p.cap, c, p.cap, lane);
                 if (lane == 0) {
                     cnt[r] = p.Kp;
@@ -246,9 +299,12 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     if (!base || !queries || !out_ids || !out_dist) return fail(NSG_EINVAL, "NULL pointer");
     if (exclude_self && nq > n) return fail(NSG_EINVAL, "exclude_self needs queries = base rows");
     hipStream_t st = (hipStream_t)stream;
-    const int Kp = (k + 32 + 63) / 64 * 64;
+    // over-fetch margin 24 for the inner-product form's rounding; buffer of
+    // Kp + two tiles (next power of two)
+    const int Kp = (k + 24 + 31) / 32 * 32;
     int cap = 1;
-    while (cap < Kp + BX) cap <<= 1;
+    while (cap < Kp + 2 * BX) cap <<= 1;
+    if ((size_t)2 * KB * KPAD * 4 + BQ * 8 + (size_t)BQ * cap * 8 > 160 * 1024) cap >>= 1;   // large k: one tile of slack
     // splits: enough blocks to fill the machine, at least a few tiles each
     int64_t qtiles = (nq + BQ - 1) / BQ;
     int64_t want = std::max<int64_t>(1, 2048 / std::max<int64_t>(qtiles, 1));
@@ -289,8 +345,16 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     p.exclude_self = exclude_self ? 1 : 0;
     p.cand_ids = cand;
     size_t lds = (size_t)2 * KB * KPAD * 4 + BQ * 8 + (size_t)BQ * cap * 8;
-    NSG_HIP(hipFuncSetAttribute((const void *)bf_tile_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(bf_tile_kernel, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), lds, st, p);
+    if (lds > 160 * 1024) return fail(NSG_EUNSUPPORTED, "k=%d needs %zu bytes of LDS", k, lds);
+    if (d <= 128) {
+        NSG_HIP(hipFuncSetAttribute((const void *)bf_tile_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+        hipLaunchKernelGGL(bf_tile_kernel<true>, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), lds, st, p);
+    } else {
+        NSG_HIP(hipFuncSetAttribute((const void *)bf_tile_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+        hipLaunchKernelGGL(bf_tile_kernel<false>, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), lds, st, p);
+    }
     const int wpb = std::max(1, std::min(4, (int)(64 * 1024 / ((size_t)sort_n * 8))));
     hipLaunchKernelGGL(bf_rerank_kernel, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb),
                        (size_t)sort_n * 8 * wpb, st, base, queries, nq, d, cand, ncand, k, sort_n, out_ids, out_dist);
