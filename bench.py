@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="sift1m_like", choices=["sift1m_like", "deep_uneven"],
+    ap.add_argument("--workload", default="sift1m_like", choices=["sift1m_like", "deep_uneven", "gist_precision"],
                     help="deep_uneven: DEEP-like unit vectors, 100k queries with uneven k and L served in "
                          "batches of 1000 by hipGraph replays of the persistent kernel (a secondary line)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -95,6 +95,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "deep_uneven":
         return uneven(args, torch, nsg, datagen, dev)
+    if args.workload == "gist_precision":
+        return precision(args, torch, nsg, datagen, dev)
     w = datagen.SIFT1M_LIKE if not args.n else datagen.scaled(datagen.SIFT1M_LIKE, args.n)
     k = 10
 
@@ -476,6 +478,93 @@ def uneven(args, torch, nsg, datagen, dev):
                    "p99_batch_ms": round(float(np.percentile(lat, 99)), 4),
                    "wall_s": round(wall, 3), "recall_by_k": rec, "autotuned": best, "index_s": round(t_idx, 1)},
     }
+    print(json.dumps(res))
+
+
+def precision(args, torch, nsg, datagen, dev):
+    """GIST-like 960-d vectors (500-component mixture, L2-normalised then scaled
+    by U[0.5, 2]), NSG R=70; 1000 queries, k=10.  For each storage format (FP32,
+    BF16, FP16, E4M3 with per-dimension scales) and pool size: QPS, recall@10
+    against the exact top-10, and the largest relative error of the returned
+    distances against FP64 distances computed on the host, for the walk's own
+    distances (decoded rows, no re-rank) and after the FP32 re-rank."""
+    n = args.n or 1_000_000
+    w = datagen.scaled(datagen.GIST1M_LIKE, n)
+    X = datagen.base(w)
+    Q = datagen.queries(w)
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    k = 10
+    t = time.time()
+    knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
+    torch.cuda.synchronize()
+    t_knn = time.time() - t
+    t = time.time()
+    graph, nav, rep = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
+    torch.cuda.synchronize()
+    t_build = time.time() - t
+    del knn
+    log(f"{w.name}: knn graph {t_knn:.1f}s, build {t_build:.1f}s, repair edges {rep}")
+    truth, _ = nsg.knn_bruteforce(Xd, Qd, k)
+    tr = truth.cpu().numpy().view(np.uint32)
+    nq = Q.shape[0]
+    X64 = None
+
+    def fp64_err(ids, dist):
+        # host FP64 distances of the returned ids (valid entries only)
+        nonlocal X64
+        ids = ids.cpu().numpy().view(np.uint32)
+        dist = dist.cpu().numpy()
+        ok = ids != 0xFFFFFFFF
+        rows = X[ids[ok].astype(np.int64)].astype(np.float64)
+        qs = np.repeat(Q.astype(np.float64), k, axis=0).reshape(nq, k, -1)[ok]
+        d64 = ((rows - qs) ** 2).sum(1)
+        return float(np.max(np.abs(dist[ok] - d64) / np.maximum(d64, 1e-30)))
+
+    out = {}
+    Ls = (20, 30, 40, 50, 60, 80, 100, 120, 150, 200, 250, 300, 400)
+    for dt in ("f32", "bf16", "f16", "e4m3"):
+        ix = nsg.load_index(Xd, graph, nav, dt)
+        rows = []
+        for L in Ls:
+            ids, dist = nsg.search(ix, Qd, k, L)
+            torch.cuda.synchronize()
+            reps = []
+            for _ in range(5):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                nsg.search(ix, Qd, k, L, out_ids=ids, out_dist=dist)
+                b.record()
+                torch.cuda.synchronize()
+                reps.append(a.elapsed_time(b))
+            ms = float(np.median(reps))
+            rec = float(np.mean([len(set(x) & set(y)) / k for x, y in zip(ids.cpu().numpy().view(np.uint32), tr)]))
+            err_rr = fp64_err(ids, dist)
+            wi, wd = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(rerank=-1))
+            err_walk = fp64_err(wi, wd)
+            rows.append(dict(L=L, qps=round(nq / (ms / 1e3), 1), recall10=round(rec, 4),
+                             max_rel_err_walk=float(f"{err_walk:.3e}"), max_rel_err_rerank=float(f"{err_rr:.3e}")))
+        ix.close()
+        out[dt] = rows
+        log(f"{dt}: " + "; ".join(f"L={r['L']} r={r['recall10']} qps={r['qps']:.0f} err {r['max_rel_err_walk']:.1e}/"
+                                  f"{r['max_rel_err_rerank']:.1e}" for r in rows))
+    # headline: QPS of each format at the smallest L with recall@10 >= 0.95
+    head = {}
+    for dt, rows in out.items():
+        hit = [r for r in rows if r["recall10"] >= args.target]
+        head[dt] = hit[0] if hit else None
+    res = {
+        "metric": "QPS at recall@10>=0.95 per storage format, 1M x 960 GIST-like, FP32 re-rank",
+        "value": head["f16"]["qps"] if head.get("f16") else None,
+        "unit": "queries/s", "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16 storage, f32 math",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {n} x {X.shape[1]} norm-scaled mixture, {nq} queries, NSG R={w.R} "
+                               f"l={w.Lb} C={w.C} from exact {w.K}-NN graph; k={k}",
+                   "at_target": head, "sweep": out, "knn_s": round(t_knn, 1), "build_s": round(t_build, 1)},
+    }
+    if head.get("f16"):
+        res["ms_per_step"] = round(nq / head["f16"]["qps"] * 1e3, 4)
     print(json.dumps(res))
 
 
