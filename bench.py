@@ -7,9 +7,10 @@ Pipeline (everything on the GPU through libnsg.so, outside the timed region):
   build     NSG (Algorithm 2: R=50, l=40, C=500) on the GPU
   truth     exact top-100 of the test queries (brute force)
   sweep     plain FP32 search over L -> the smallest L with mean recall@10 >= 0.95
-  learned   per-query expansion budgets at FP16 pool sizes L16, 1.25 L16, 1.5 L16
-            (L16: the plain FP16 one): budget traces, labels, MLP training and
-            calibration each; the fastest on held-out training queries is kept
+  learned   per-query expansion budgets at FP16 pool sizes L16 + {0, 4, 8, 12, 16}
+            and 1.25 L16 (L16: the plain FP16 one): budget traces, labels, MLP
+            training and calibration each; the fastest on held-out training
+            queries is kept
 Timed: `--warmup` untimed steps, then `--steps` steps; a step is one search
 call over the whole 10k-query batch (queries already resident in HBM), for
 each of the two configurations.  Prints ONE JSON line.
@@ -176,9 +177,10 @@ def main():
 
     # ---------------- learned early stop (FP16 index) ----------------
     # The early stop gives each query an expansion budget at a fixed pool size.
-    # Pool sizes at and above the plain FP16 one are tried; each gets its own
-    # traces, network and calibration on held-out training queries, and the
-    # fastest on held-out training queries (never the test queries) is kept.
+    # Pool sizes at and a little above the plain FP16 one are tried (budgets
+    # cost recall, a larger pool buys it back); each gets its own traces,
+    # network and calibration on held-out training queries, and the fastest on
+    # held-out training queries (never the test queries) is kept.
     ntr = args.train
     Tq = torch.from_numpy(datagen.train_queries(w, ntr)).to(dev)
     ttruth, _ = nsg.knn_bruteforce(Xd, Tq, k)
@@ -187,7 +189,7 @@ def main():
     hq_truth = ttruth[n_fit:].contiguous()
     L_base = f16[0] if f16 else 512
     best = None
-    for L_l in sorted({L_base, int(round(L_base * 1.25)), int(round(L_base * 1.5))}):
+    for L_l in sorted({L_base + dl for dl in (0, 4, 8, 12, 16)} | {int(round(L_base * 1.25))}):
         L_l = min(L_l, 512)
         t = time.time()
         tr = ls.traces(ix16, Tq, ttruth, L_l, k=k)

@@ -127,7 +127,7 @@ const int64_t kPersistentMinBatch = 4096;
 // a query visits roughly 25 nodes per pool entry; size the filter to that
 // (it forgets beyond, which only costs recomputation)
 int default_hash_bits(int L) {
-    int want = L * 12, bits = 10;
+    int want = L * 24, bits = 10;
     while ((1 << bits) < want && bits < 13) ++bits;
     return bits;
 }

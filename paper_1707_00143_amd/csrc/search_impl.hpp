@@ -185,12 +185,16 @@ __device__ inline int stop_predict(const KParams &p, const float *xbuf, int lane
 }
 
 // MODE selects what is compiled in: 0 the plain search only; 1 also the
-// learned early stop (and the chosen pool size output); 2 every option
+// learned early stop (and the chosen budget output); 2 every option
 // (feature capture, visited recording, pool output, counters,
 // own-row visit).  Options left out keep registers free for occupancy.
 // NCH: pool chunks of 64 held in registers (NCH * 64 >= L_alloc).
+// Occupancy targets for the common 2-chunk pool: the plain search at 5 waves
+// per SIMD (<= 96 registers; a few cold values go to scratch, measured
+// faster), the learned-stop variant at 4 (<= 128; it needs 130 otherwise).
 template <int DT, int LPR, int CPL, int MODE, int NCH>
-__global__ void __launch_bounds__(256) search_kernel(KParams p) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 2 ? (MODE == 0 ? 5 : (MODE == 1 ? 4 : 1)) : 1)))
+search_kernel(KParams p) {
     constexpr int EPC = Fmt<DT>::EPC;
     constexpr bool FULL = MODE == 2;
     constexpr bool LEARN = MODE >= 1;
