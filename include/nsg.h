@@ -112,15 +112,14 @@ typedef struct nsg_search_opts {
     int32_t waves_per_block; /* 0: autotuned / default */
     int32_t hash_slots;      /* visited-filter slots per query (power of 2); 0: default */
     int32_t blocks;          /* persistent grid size; 0: one wave per resident slot */
-    int32_t learned_stop;    /* 1: use the loaded early-stop model (needs L >= 16) */
+    int32_t learned_stop;    /* 1: use the loaded early-stop model (queries with L >= 16) */
     int32_t rerank;          /* 0: default (on for reduced storage), 1: on, -1: off */
     int64_t *hops;           /* device [nq] expansions per query, or NULL */
     int64_t *ndist;          /* device [nq] distance evaluations per query, or NULL */
     int32_t *budget;         /* device [nq] expansion budget chosen by the early stop (0: none), or NULL */
-    float *features;         /* device [nq][d + 3] early-stop features (query, best pool
-                                distance, 1st/10th pool distance ratio, hops) right after
-                                expansion `feature_hop`; NaN rows for searches that ended
-                                earlier; or NULL */
+    float *features;         /* device [nq][NSG_STOP_FEATURES] early-stop features (see the
+                                network below) after expansion `feature_hop`; NaN rows for
+                                searches that ended earlier; or NULL */
     uint32_t *pool_ids;      /* device [nq][pool_stride] final pool ids, or NULL */
     float *pool_dist;        /* device [nq][pool_stride] final pool distances */
     int32_t pool_stride;
@@ -155,7 +154,8 @@ typedef struct nsg_search_graph nsg_search_graph;   /* opaque, owned by the libr
  * Capture one nsg_search_batched call (same arguments) into a HIP graph and
  * instantiate it.  The buffers are bound at capture: refill `queries` (and
  * k / L) in place, then nsg_search_graph_launch replays the whole batch with
- * one launch.  With opts->persistent the graph owns its work counter.
+ * one launch.  With opts->persistent the graph owns its work counter; with
+ * early-stop features or the learned stop it owns the two-phase scratch.
  */
 int nsg_search_graph_create(const nsg_index *idx, const float *queries, int64_t nq,
                             const int32_t *k, const int32_t *L, int32_t k_scalar,
@@ -217,18 +217,28 @@ int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t *knn,
 /* ------------------------------------------------------------------------ */
 
 /*
- * Network: in = d + 3 features (query, best pool distance, ratio of the 1st
- * to the 10th pool distance, hop count) taken after `hop` expansions,
- * z-scored with mean[in] / inv_std[in]; two ReLU hidden layers of h units;
- * one linear output y = predicted log2 of the expansion budget.  The query
- * then stops after B = max(hop, smallest grid value >= c * 2^y) expansions
- * (the largest grid value if none is), or earlier when no unchecked entry
- * remains: its result is the plain search's after min(B, its own expansion
- * count) expansions, with the same L.  A non-finite y sets no budget.
+ * Features (NSG_STOP_FEATURES = 15, FP32), taken from the search state after
+ * `hop` expansions; d_r is the distance of pool rank min(r, size - 1) (FP32
+ * squared distance of the search format), d_s the distance to the start node:
+ *   0 ln(1 + d_0)        1 d_0 / d_9 (1 if d_9 = 0)
+ *   2 ln(1 + d_s)        3 ln(1 + d_0) - ln(1 + d_s)
+ *   4..13 ln(1 + d_r) - ln(1 + d_0) for r = 1, 2, 4, 9, 14, 19, 29, 39, 59, 83
+ *   14 valid neighbour entries read per expansion so far
+ * Network: z-scored with mean[in] / inv_std[in] (in = NSG_STOP_FEATURES); two
+ * ReLU hidden layers of h <= 64 units; one linear output y = predicted log2
+ * of the expansion budget (FP32 throughout).  The query then stops after
+ * B = max(hop, smallest grid value >= c * 2^y) expansions (the largest grid
+ * value if none is), or earlier when no unchecked entry remains: its result
+ * is the plain search's after min(B, its own expansion count) expansions,
+ * with the same L.  A non-finite y sets no budget.
+ * The decision is fused into the search loop: after expansion `hop` the
+ * wavefront forms the features from its pool, evaluates the network and
+ * continues with the budget.
  * blob (host) holds FP32: mean[in], inv_std[in], W1[h][in], b1[h],
  * W2[h][h], b2[h], W3[h], b3, then `grid_n` FP32 grid values (expansion
  * counts in [1, 2^20]) ascending.
  */
+#define NSG_STOP_FEATURES 15
 int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes,
                         int32_t in, int32_t h, int32_t hop, int32_t grid_n);
 

@@ -21,6 +21,8 @@ Parity status per function (see the tests named):
                   (test_oracle_precision)
   mlp             pinned: central finite differences and torch FP64 autograd
                   (test_oracle_mlp)
+  stop_features   pinned: hand-worked state with literal expected values
+                  (test_oracle_mlp)
 """
 from __future__ import annotations
 
@@ -335,6 +337,27 @@ def adam_step(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     _check(_get().oracle_adam_step(_p(params), _p(grad), _p(m), _p(v), params.size, int(t),
                                    lr, b1, b2, eps), "adam")
+
+
+FEATURE_RANKS = (1, 2, 4, 9, 14, 19, 29, 39, 59, 83)
+
+
+def stop_features(pool_dist, d_start, nedges, hops):
+    """Early-stop features of a search state (FP64; not in the paper, the
+    library's own definition).  pool_dist: the sorted pool distances after
+    `hops` expansions; d_start: distance to the start node; nedges: valid
+    neighbour entries read by those expansions.  d_r is the distance at rank
+    min(r, size - 1).  Returns 15 values: ln(1 + d_0), d_0 / d_9 (1 if
+    d_9 = 0), ln(1 + d_start), ln(1 + d_0) - ln(1 + d_start), then
+    ln(1 + d_r) - ln(1 + d_0) for r in FEATURE_RANKS, then nedges / hops."""
+    import math
+    d = [float(x) for x in pool_dist]
+    at = lambda r: d[min(r, len(d) - 1)]
+    l0 = math.log1p(at(0))
+    f = [l0, at(0) / at(9) if at(9) > 0 else 1.0, math.log1p(d_start), l0 - math.log1p(d_start)]
+    f += [math.log1p(at(r)) - l0 for r in FEATURE_RANKS]
+    f.append(nedges / hops if hops > 0 else 0.0)
+    return np.asarray(f, np.float64)
 
 
 def recall_at_k(found_ids, gt_ids, k):

@@ -32,6 +32,9 @@ class NSGError(RuntimeError):
         self.code = code
 
 
+STOP_FEATURES = 15   # early-stop features per query (see nsg.h)
+
+
 class SearchOpts(ctypes.Structure):
     _fields_ = [
         ("persistent", ctypes.c_int32),

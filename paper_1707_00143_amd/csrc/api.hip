@@ -156,9 +156,7 @@ extern "C" void nsg_free_index(nsg_index *idx) {
     hipFree(idx->base_lp);
     hipFree(idx->scales);
     hipFree(idx->graph);
-    hipFree(idx->stop.f32);
-    hipFree(idx->stop.w16);
-    hipFree(idx->stop.grid);
+    hipFree(idx->stop.blob);
     delete idx;
 }
 
@@ -254,7 +252,7 @@ static int check_search_common(const nsg_index *idx, const float *queries, int64
     return NSG_OK;
 }
 
-static int stop_ready(const nsg_index *idx) { return idx->stop.enabled && idx->stop.f32 && idx->stop.grid; }
+static int stop_ready(const nsg_index *idx) { return idx->stop.enabled && idx->stop.blob; }
 
 
 extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
@@ -286,6 +284,13 @@ extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq
     return launch_search(a);
 }
 
+// visited-filter size of a batched call: the caller's, else the default for L
+static int opts_hash_bits(int L_cap, const nsg_search_opts &o) {
+    int hb = default_hash_bits(L_cap);
+    if (o.hash_slots) { hb = 0; while ((1 << hb) < o.hash_slots) ++hb; }
+    return hb;
+}
+
 extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, int64_t nq, const int32_t *k,
                                   const int32_t *L, int32_t k_scalar, int32_t L_scalar, int32_t out_stride,
                                   uint32_t *out_ids, float *out_dist, const nsg_search_opts *opts,
@@ -306,6 +311,7 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
         return fail(NSG_EINVAL, "hash_slots out of range [64, 16384]");
     if (o.waves_per_block < 0 || o.waves_per_block > 16) return fail(NSG_EINVAL, "waves_per_block out of range");
     if (o.pool_ids && (o.pool_stride < 1 || !o.pool_dist)) return fail(NSG_EINVAL, "pool output needs stride and dist");
+    if (o.learned_stop < 0 || o.learned_stop > 1) return fail(NSG_EINVAL, "learned_stop must be 0 or 1");
     if (o.learned_stop && !stop_ready(idx)) return fail(NSG_ESTATE, "no early-stop model loaded and enabled");
     if (o.feature_hop < 0) return fail(NSG_EINVAL, "feature_hop < 0");
     if (o.max_hops < 0) return fail(NSG_EINVAL, "max_hops < 0");
@@ -325,11 +331,9 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.out_stride = out_stride;
     a.out_ids = out_ids;
     a.out_dist = out_dist;
-    a.learned = o.learned_stop ? 1 : 0;
+    a.learned = o.learned_stop;
     a.L_cap = L_scalar;
-    int hb = default_hash_bits(a.L_cap);
-    if (o.hash_slots) { hb = 0; while ((1 << hb) < o.hash_slots) ++hb; }
-    a.hash_bits = hb;
+    a.hash_bits = opts_hash_bits(a.L_cap, o);
     a.waves_per_block = o.waves_per_block;
     a.persistent = o.persistent;
     a.blocks = o.blocks;
@@ -352,6 +356,7 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     return launch_search(a);
 }
 
+
 // ---------------------------------------------------------------------------
 // learned early stop: model residency
 // ---------------------------------------------------------------------------
@@ -359,42 +364,45 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
                                    int32_t hop, int32_t grid_n) {
     clear_error();
     if (!idx || !blob) return fail(NSG_EINVAL, "NULL index or blob");
-    if (in != idx->d + 3) return fail(NSG_EINVAL, "model input %d must be d + 3 = %d", in, idx->d + 3);
+    if (in != kStopFeatures) return fail(NSG_EINVAL, "model input %d must be %d features", in, kStopFeatures);
     if (h < 1 || h > 64) return fail(NSG_EUNSUPPORTED, "hidden width %d outside [1, 64]", h);
     if (hop < 1) return fail(NSG_EINVAL, "hop must be >= 1");
     if (grid_n < 1 || grid_n > 256) return fail(NSG_EINVAL, "grid_n out of range [1, 256]");
     const size_t nf = (size_t)2 * in + (size_t)h * in + h + (size_t)h * h + h + h + 1 + grid_n;
     if (bytes != nf * sizeof(float)) return fail(NSG_EINVAL, "blob has %zu bytes, expected %zu", bytes, nf * 4);
     const float *b = static_cast<const float *>(blob);
-    const float *mean = b, *istd = b + in, *W1 = istd + in, *b1 = W1 + (size_t)h * in, *W2 = b1 + h;
-    const float *b2 = W2 + (size_t)h * h, *W3 = b2 + h, *b3 = W3 + h, *grid = b3 + 1;
+    const float *grid = b + nf - grid_n;
     for (int i = 0; i < grid_n; ++i) {
         if (!(grid[i] >= 1.0f && grid[i] <= 1048576.0f)) return fail(NSG_EINVAL, "grid value out of [1, 2^20]");
         if (i && grid[i] <= grid[i - 1]) return fail(NSG_EINVAL, "grid must be strictly ascending");
     }
-    std::vector<float> f32;
-    f32.insert(f32.end(), mean, mean + in);
-    f32.insert(f32.end(), istd, istd + in);
-    f32.insert(f32.end(), b1, b1 + h);
-    f32.insert(f32.end(), b2, b2 + h);
-    f32.push_back(*b3);
-    std::vector<_Float16> w;
-    w.resize((size_t)in * h + (size_t)h * h + h);
-    for (int i = 0; i < in; ++i)
-        for (int j = 0; j < h; ++j) w[(size_t)i * h + j] = (_Float16)W1[(size_t)j * in + i];
-    _Float16 *w2 = w.data() + (size_t)in * h;
-    for (int i = 0; i < h; ++i)
-        for (int j = 0; j < h; ++j) w2[(size_t)i * h + j] = (_Float16)W2[(size_t)j * h + i];
-    for (int j = 0; j < h; ++j) w2[(size_t)h * h + j] = (_Float16)W3[j];
-    StopModel sm;
-    if (hipMalloc(&sm.f32, f32.size() * 4) != hipSuccess || hipMalloc(&sm.w16, w.size() * 2) != hipSuccess ||
-        hipMalloc(&sm.grid, (size_t)grid_n * 4) != hipSuccess) {
-        hipFree(sm.f32); hipFree(sm.w16); hipFree(sm.grid);
-        return fail(NSG_ENOMEM, "model allocation failed");
+    // kernel layout: W1T[in][64], W2T[64][64], b1[64], b2[64], W3[64], b3,
+    // mean[in], inv_std[in], grid[grid_n] (hidden units past h are zero)
+    const float *mean = b, *istd = b + in, *W1 = istd + in, *b1 = W1 + (size_t)h * in, *W2 = b1 + h;
+    const float *b2 = W2 + (size_t)h * h, *W3 = b2 + h, *b3 = W3 + h;
+    std::vector<float> pl((size_t)in * 64 + 64 * 64 + 3 * 64 + 1 + 2 * (size_t)in + grid_n, 0.0f);
+    float *pW1T = pl.data(), *pW2T = pW1T + (size_t)in * 64, *pb1 = pW2T + 64 * 64, *pb2 = pb1 + 64;
+    float *pW3 = pb2 + 64, *pb3 = pW3 + 64, *pmean = pb3 + 1, *pistd = pmean + in, *pgrid = pistd + in;
+    for (int j = 0; j < h; ++j) {
+        for (int i = 0; i < in; ++i) pW1T[(size_t)i * 64 + j] = W1[(size_t)j * in + i];
+        for (int k = 0; k < h; ++k) pW2T[(size_t)k * 64 + j] = W2[(size_t)j * h + k];
+        pb1[j] = b1[j];
+        pb2[j] = b2[j];
+        pW3[j] = W3[j];
     }
-    NSG_HIP(hipMemcpy(sm.f32, f32.data(), f32.size() * 4, hipMemcpyHostToDevice));
-    NSG_HIP(hipMemcpy(sm.w16, w.data(), w.size() * 2, hipMemcpyHostToDevice));
-    NSG_HIP(hipMemcpy(sm.grid, grid, (size_t)grid_n * 4, hipMemcpyHostToDevice));
+    *pb3 = *b3;
+    for (int i = 0; i < in; ++i) {
+        pmean[i] = mean[i];
+        pistd[i] = istd[i];
+    }
+    for (int i = 0; i < grid_n; ++i) pgrid[i] = grid[i];
+    StopModel sm;
+    if (hipMalloc(&sm.blob, pl.size() * 4) != hipSuccess) return fail(NSG_ENOMEM, "model allocation failed");
+    hipError_t e = hipMemcpy(sm.blob, pl.data(), pl.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(sm.blob);
+        return fail(NSG_EDEVICE, "model copy failed: %s", hipGetErrorString(e));
+    }
     sm.in = in;
     sm.h = h;
     sm.hop = hop;
@@ -402,9 +410,7 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
     sm.enabled = idx->stop.enabled;
     sm.calib_c = idx->stop.calib_c;
     hipDeviceSynchronize();
-    hipFree(idx->stop.f32);
-    hipFree(idx->stop.w16);
-    hipFree(idx->stop.grid);
+    hipFree(idx->stop.blob);
     idx->stop = sm;
     return NSG_OK;
 }
@@ -412,7 +418,7 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
 extern "C" int nsg_set_stop_mode(nsg_index *idx, int32_t enabled, float calib_c) {
     clear_error();
     if (!idx) return fail(NSG_EINVAL, "index is NULL");
-    if (enabled && !idx->stop.f32) return fail(NSG_ESTATE, "no early-stop model loaded");
+    if (enabled && !idx->stop.blob) return fail(NSG_ESTATE, "no early-stop model loaded");
     if (!(calib_c > 0.0f) || !std::isfinite(calib_c)) return fail(NSG_EINVAL, "calibration must be finite and > 0");
     idx->stop.enabled = enabled ? 1 : 0;
     idx->stop.calib_c = calib_c;

@@ -29,10 +29,13 @@ void clear_error();
     } while (0)
 
 // ---- the index object ------------------------------------------------------
+// Early-stop features per query, taken after the decision hop (stop_feature
+// in search_impl.hpp).
+constexpr int kStopFeatures = 15;
+
 struct StopModel {
-    float *f32 = nullptr;      // device: mean[in], inv_std[in], b1[h], b2[h], b3
-    void *w16 = nullptr;       // device FP16: W1T[in][h], W2T[h][h], W3[h]
-    float *grid = nullptr;     // device: grid values (ascending)
+    float *blob = nullptr;     // device FP32, kernel layout: W1T[in][64], W2T[64][64], b1[64], b2[64],
+                               // W3[64], b3, mean[in], inv_std[in], grid[grid_n] (units past h zero)
     int in = 0, h = 0, hop = 0, grid_n = 0;
     int enabled = 0;
     float calib_c = 1.0f;

@@ -23,17 +23,18 @@ void pick_layout(int chunks, int max_cpl, int *lpr, int *cpl) {
 __global__ void reset_counter_kernel(unsigned int *c) { if (threadIdx.x == 0) c[0] = 0u; }
 
 kfn_t pick_search_kernel_f32(int lpr, int cpl, int nch);
-kfn_t pick_search_kernel_f32_learn(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_f32_stop(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_f32_full(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_bf16(int lpr, int cpl, int nch);
-kfn_t pick_search_kernel_bf16_learn(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_bf16_stop(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_bf16_full(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_f16(int lpr, int cpl, int nch);
-kfn_t pick_search_kernel_f16_learn(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_f16_stop(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_f16_full(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_e4m3(int lpr, int cpl, int nch);
-kfn_t pick_search_kernel_e4m3_learn(int lpr, int cpl, int nch);
+kfn_t pick_search_kernel_e4m3_stop(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_e4m3_full(int lpr, int cpl, int nch);
+
 
 int launch_search(const SearchArgs &a) {
     const nsg_index *ix = a.idx;
@@ -66,9 +67,7 @@ int launch_search(const SearchArgs &a) {
     p.hops = a.hops;
     p.ndist = a.ndist;
     p.nedges = a.nedges;
-    p.budget = a.budget;
     p.max_hops = a.max_hops;
-    p.features = a.features;
     p.pool_ids = a.pool_ids;
     p.pool_dist = a.pool_dist;
     p.pool_stride = a.pool_stride;
@@ -77,30 +76,28 @@ int launch_search(const SearchArgs &a) {
     p.vis_cnt = a.vis_cnt;
     p.vis_cap = a.vis_cap;
     p.self_offset = a.self_offset;
+    // learned early stop and feature capture, fused into the search loop
+    p.features = a.features;
+    p.budget = a.budget;
     p.learned = 0;
-    p.feat_cap = a.features ? ((ix->d + 3 + 3) & ~3) : 0;
-    p.s_in = ix->d + 3;
     p.s_hop = a.feature_hop > 0 ? a.feature_hop : 16;
     if (a.learned) {
         const StopModel &sm = ix->stop;
+        if (!sm.blob) return fail(NSG_ESTATE, "no early-stop model loaded");
+        if (a.features && a.feature_hop > 0 && a.feature_hop != sm.hop)
+            return fail(NSG_EINVAL, "feature hop differs from the model's decision hop");
         p.learned = 1;
-        p.stop_f32 = sm.f32;
-        p.stop_w = reinterpret_cast<const _Float16 *>(sm.w16);
-        p.grid = sm.grid;
+        p.stop_plan = sm.blob;
         p.s_in = sm.in;
-        p.s_h = sm.h;
         p.s_hop = sm.hop;
         p.grid_n = sm.grid_n;
         p.calib_c = sm.calib_c;
-        p.feat_cap = (sm.in + 3) & ~3;
-        if (a.features && sm.hop != p.s_hop && a.feature_hop > 0)
-            return fail(NSG_EINVAL, "feature hop differs from the model's decision hop");
     }
     int L_alloc = 1;
     while (L_alloc < a.L_cap) L_alloc <<= 1;
     p.L_alloc = L_alloc;
-    // pool, visited filter, candidate ids and distances, features
-    size_t per_wave = (size_t)L_alloc * 8 + ((size_t)4 << a.hash_bits) + kMaxR * 8 + (size_t)p.feat_cap * 4;
+    // pool, visited filter, candidate ids and distances
+    size_t per_wave = (size_t)L_alloc * 8 + ((size_t)4 << a.hash_bits) + kMaxR * 8;
     per_wave = (per_wave + 15) & ~(size_t)15;
     p.lds_per_wave = (int)per_wave;
     int wpb = a.waves_per_block;
@@ -118,26 +115,25 @@ int launch_search(const SearchArgs &a) {
         if (cpl == 3) cpl = 4;
         if (cpl > 4) return fail(NSG_EINVAL, "lanes_per_row=%d too small for %d chunks per row", lpr, ix->row_chunks);
     }
-    const bool full = a.features || a.vis_ids || a.pool_ids || a.hops || a.ndist || a.nedges ||
-                      a.self_offset >= 0;
-    const int mode = full ? 2 : (a.learned || a.budget) ? 1 : 0;
+    const bool full = a.vis_ids || a.pool_ids || a.hops || a.ndist || a.nedges || a.self_offset >= 0;
+    const int mode = full ? 2 : (a.learned || a.features || a.budget) ? 1 : 0;
     const int nch = L_alloc <= 128 ? 2 : L_alloc <= 256 ? 4 : 8;   // pool registers per lane: 2 * nch
     kfn_t fn = nullptr;
     switch (ix->storage) {
     case NSG_F32: fn = mode == 2 ? pick_search_kernel_f32_full(lpr, cpl, nch)
-                       : mode == 1 ? pick_search_kernel_f32_learn(lpr, cpl, nch)
+                       : mode == 1 ? pick_search_kernel_f32_stop(lpr, cpl, nch)
                                    : pick_search_kernel_f32(lpr, cpl, nch);
         break;
     case NSG_BF16: fn = mode == 2 ? pick_search_kernel_bf16_full(lpr, cpl, nch)
-                       : mode == 1 ? pick_search_kernel_bf16_learn(lpr, cpl, nch)
+                       : mode == 1 ? pick_search_kernel_bf16_stop(lpr, cpl, nch)
                                    : pick_search_kernel_bf16(lpr, cpl, nch);
         break;
     case NSG_F16: fn = mode == 2 ? pick_search_kernel_f16_full(lpr, cpl, nch)
-                       : mode == 1 ? pick_search_kernel_f16_learn(lpr, cpl, nch)
+                       : mode == 1 ? pick_search_kernel_f16_stop(lpr, cpl, nch)
                                    : pick_search_kernel_f16(lpr, cpl, nch);
         break;
     case NSG_E4M3: fn = mode == 2 ? pick_search_kernel_e4m3_full(lpr, cpl, nch)
-                       : mode == 1 ? pick_search_kernel_e4m3_learn(lpr, cpl, nch)
+                       : mode == 1 ? pick_search_kernel_e4m3_stop(lpr, cpl, nch)
                                    : pick_search_kernel_e4m3(lpr, cpl, nch);
         break;
     }

@@ -20,13 +20,11 @@ struct KParams {
     int k_scalar, L_scalar, out_stride;
     uint32_t *out_ids;
     float *out_dist;
-    int L_cap, L_alloc, hash_bits, lds_per_wave, feat_cap;
+    int L_cap, L_alloc, hash_bits, lds_per_wave;
     int rerank;
     unsigned int *counter;
     int64_t *hops, *ndist, *nedges;
-    int32_t *budget;             // chosen expansion budget per query (learned stop), or NULL
     int max_hops;                // expansion budget for every query (0: none)
-    float *features;
     uint32_t *pool_ids;
     float *pool_dist;
     int pool_stride;
@@ -35,13 +33,13 @@ struct KParams {
     int32_t *vis_cnt;
     int vis_cap;
     int64_t self_offset;         // >= 0: query i is base row self_offset + i; its own row is visited at the end
-    // learned early stop
-    const float *stop_f32;       // mean[in], inv_std[in], b1[h], b2[h], b3
-    const _Float16 *stop_w;      // W1T[in][h], W2T[h][h], W3[h]
-    const float *grid;
-    int s_in, s_h, s_hop, grid_n;
+    // learned early stop, fused into the search loop (see stop_decide)
+    const float *stop_plan;      // network (kernel layout, see stop_decide)
+    int32_t *budget;             // chosen budget per query (0: none), or NULL
+    float *features;             // raw features [nq][kStopFeatures] after expansion s_hop, or NULL
+    int s_in, s_hop, grid_n;
     float calib_c;
-    int learned;
+    int learned;                 // 1: queries with L >= 16 stop at their budget
 };
 
 // exact FP32 squared distances over the FP32 rows (re-rank): 16 lanes per
@@ -114,90 +112,95 @@ __device__ inline void lds_sort(uint64_t *a, int n, int cap, int lane) {
     }
 }
 
-// early-stop features after the decision expansion: the query, the best pool
-// distance, the ratio of the 1st to the 10th pool distance, the hop count.
-// Written raw to p.features (if given and WF) and z-scored into xbuf (if learned).
-template <bool WF>
-__device__ inline void stop_features(const KParams &p, const float *q, float d0, float d9,
-                                     int64_t hops, float *xbuf, int lane, int64_t qi) {
-    const int in = p.d + 3;
-    const float *sf = p.stop_f32;
-    asm volatile("" : "+s"(sf));   // not hoisted out of the search loop
-    for (int i = lane; i < in; i += 64) {
-        float f;
-        if (i < p.d) f = q[i];
-        else if (i == p.d) f = d0;
-        else if (i == p.d + 1) f = d9 > 0.0f ? d0 / d9 : 1.0f;
-        else f = (float)hops;
-        if (WF && p.features) p.features[qi * (int64_t)in + i] = f;
-        if (p.learned) xbuf[i] = (f - sf[i]) * sf[in + i];
+// Feature i (< kStopFeatures) of a search state, FP32.  dist(r) is the
+// distance of pool rank r (r < size).
+template <typename DistAt>
+__device__ inline float stop_feature(int i, DistAt dist, int size, float dstart, int64_t ne, int64_t hops) {
+    constexpr int ranks[10] = {1, 2, 4, 9, 14, 19, 29, 39, 59, 83};
+    auto at = [&](int r) { return dist(r < size ? r : size - 1); };
+    const float d0 = at(0);
+    const float l0 = log1pf(d0);
+    if (i == 0) return l0;
+    if (i == 1) {
+        const float d9 = at(9);
+        return d9 > 0.0f ? d0 / d9 : 1.0f;
     }
-    wave_sync();
+    if (i == 2) return log1pf(dstart);
+    if (i == 3) return l0 - log1pf(dstart);
+    if (i < 14) {
+        int r = 83;
+#pragma unroll
+        for (int j = 0; j < 10; ++j) r = (i - 4 == j) ? ranks[j] : r;
+        return log1pf(at(r)) - l0;
+    }
+    return hops > 0 ? (float)ne / (float)hops : 0.0f;
 }
 
-// learned early stop: z-scored features in xbuf -> MLP (FP16 weights, FP32
-// accumulate) -> y = log2 pool size -> L_hat on the grid
-__device__ inline int stop_predict(const KParams &p, const float *xbuf, int lane) {
-    const int in = p.s_in, h = p.s_h;
-    // the model is the same for every query: opaque base pointers keep the
-    // compiler from hoisting its loads out of the search loop (they would
-    // hold registers through every expansion)
-    const float *sf = p.stop_f32;
-    const _Float16 *W1T = p.stop_w;
-    asm volatile("" : "+s"(sf), "+s"(W1T));
-    const float *b1 = sf + 2 * in;
-    const float *b2 = b1 + h;
-    const float b3 = b2[h];
-    const _Float16 *W2T = W1T + (int64_t)in * h;
-    const _Float16 *W3 = W2T + (int64_t)h * h;
-    float a1 = 0.0f;
-    if (lane < h) {
-        float s = b1[lane];
-#pragma unroll 4
-        for (int i = 0; i < in; ++i) s = fmaf((float)W1T[(int64_t)i * h + lane], xbuf[i], s);
-        a1 = s > 0.0f ? s : 0.0f;
+// The learned stop's decision for one query, after the decision hop: the
+// features of its pool (pool[0 .. size) in LDS), the raw features to
+// `features` (if given), then, if `plan` is given, the network (W1T[in][64],
+// W2T[64][64], b1[64], b2[64], W3[64], b3, mean[in], inv_std[in],
+// grid[grid_n]; hidden units past h are zero).  Returns the grid index of the
+// budget (-1: no budget for a non-finite output) and the budget in *B (at
+// least hop; 0 for none).  Not inlined: it runs once per query and would
+// otherwise hold registers through the whole search loop.
+__device__ __attribute__((noinline)) int stop_decide(const float *plan, int in, int grid_n, float calib_c, int hop,
+                                                     const uint64_t *pool, int size, float dstart, int64_t ne,
+                                                     int64_t hops, float *features, int lane, int *B) {
+    float f = 0.0f;
+    if (lane < kStopFeatures)
+        f = stop_feature(lane, [&](int r) { return key_dist(pool[r]); }, size, dstart, ne, hops);
+    if (features && lane < kStopFeatures) features[lane] = f;
+    *B = 0;
+    if (!plan) return -1;
+    const float *W1T = plan;
+    const float *W2T = W1T + in * 64, *b1 = W2T + 64 * 64, *b2 = b1 + 64, *W3 = b2 + 64, *b3 = W3 + 64;
+    const float *mean = b3 + 1, *istd = mean + in, *grid = istd + in;
+    const float x = lane < in ? (f - mean[lane < in ? lane : 0]) * istd[lane < in ? lane : 0] : 0.0f;
+    float s1 = b1[lane];
+    for (int i = 0; i < in; ++i) {
+        const float xi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
+        s1 = fmaf(W1T[i * 64 + lane], xi, s1);
     }
-    float a2 = 0.0f;
-    {
-        float s = lane < h ? b2[lane] : 0.0f;
-#pragma unroll 4
-        for (int j = 0; j < h; ++j) {
-            float aj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a1), j));
-            if (lane < h) s = fmaf((float)W2T[j * h + lane], aj, s);
-        }
-        a2 = (lane < h && s > 0.0f) ? s : 0.0f;
+    const float a1 = s1 > 0.0f ? s1 : 0.0f;
+    float s2 = b2[lane];
+#pragma unroll 8
+    for (int k = 0; k < 64; ++k) {
+        const float ak = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a1), k));
+        s2 = fmaf(W2T[k * 64 + lane], ak, s2);
     }
-    float o = lane < h ? (float)W3[lane] * a2 : 0.0f;
+    const float a2 = s2 > 0.0f ? s2 : 0.0f;
+    float o = W3[lane] * a2;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) o += __shfl_xor(o, off);
-    o += b3;
-    wave_sync();
-    if (!isfinite(o)) return 0x7FFFFFFF;   // no budget: the plain search
-    float t = p.calib_c * exp2f(o);
-    int pick = p.grid_n > 0 ? (int)p.grid[p.grid_n - 1] : 0x7FFFFFFF;
-    for (int b = 0; b < p.grid_n; b += 64) {
-        int i = b + lane;
-        bool ge = i < p.grid_n && p.grid[i] >= t;
-        uint64_t bm = __ballot(ge);
-        if (bm) { pick = (int)p.grid[b + __ffsll((long long)bm) - 1]; break; }
+    o += b3[0];
+    const float t = calib_c * exp2f(o);
+    if (!isfinite(t)) { *B = 0; return -1; }
+    int gi = grid_n - 1;   // smallest grid value >= t, else the largest
+    for (int b = 0; b < grid_n; b += 64) {
+        const int i = b + lane;
+        const uint64_t bm = __ballot(i < grid_n && grid[i] >= t);
+        if (bm) { gi = b + __ffsll((long long)bm) - 1; break; }
     }
-    return pick < p.s_hop ? p.s_hop : pick;
+    const int v = (int)grid[gi];
+    *B = v < hop ? hop : v;
+    return gi;
 }
 
 // MODE selects what is compiled in: 0 the plain search only; 1 also the
-// learned early stop (and the chosen budget output); 2 every option
-// (feature capture, visited recording, pool output, counters,
-// own-row visit).  Options left out keep registers free for occupancy.
+// learned early stop and the feature capture at the decision hop; 2 every
+// option (visited recording, pool output, counters, own-row visit).  Options
+// left out keep registers free for occupancy.
 // NCH: pool chunks of 64 held in registers (NCH * 64 >= L_alloc).
 // Occupancy targets for the common 2-chunk pool: the plain search at 5 waves
 // per SIMD (<= 96 registers; a few cold values go to scratch, measured
-// faster), the learned-stop variant at 4 (<= 128; it needs 130 otherwise).
+// faster), the learned-stop variant at 4.
 template <int DT, int LPR, int CPL, int MODE, int NCH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 2 ? (MODE == 0 ? 5 : (MODE == 1 ? 4 : 1)) : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 2 ? (MODE <= 1 ? 5 : 1) : 1)))
 search_kernel(KParams p) {
     constexpr int EPC = Fmt<DT>::EPC;
     constexpr bool FULL = MODE == 2;
-    constexpr bool LEARN = MODE >= 1;
+    constexpr bool STOP = MODE >= 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -207,7 +210,6 @@ search_kernel(KParams p) {
     uint32_t *hash = reinterpret_cast<uint32_t *>(pool + p.L_alloc);
     uint32_t *cid = hash + (1 << p.hash_bits);          // candidate ids
     float *cdist = reinterpret_cast<float *>(cid + kMaxR);   // and distances
-    float *xbuf = cdist + kMaxR;                              // early-stop features
     const int H = 1 << p.hash_bits;
 
     int64_t qi;
@@ -224,12 +226,14 @@ search_kernel(KParams p) {
         kq = kq < 0 ? 0 : (kq > p.out_stride ? p.out_stride : kq);
         int Lq = p.L_arr ? p.L_arr[qi] : p.L_scalar;
         Lq = Lq < 1 ? 1 : (Lq > p.L_cap ? p.L_cap : Lq);
-        const bool learned = LEARN && p.learned && Lq >= 16;
         const int Lcur = Lq;
         // expansion budget: the caller's, and after the decision hop the
         // learned one (the search stops early, never later, than plain)
         int64_t hcap = p.max_hops > 0 ? p.max_hops : INT64_MAX;
-        int chosen = 0;
+        // decision hop: features (if captured) and the learned budget
+        const bool learn_q = STOP && p.learned && Lq >= 16;
+        bool decide = STOP && (learn_q || p.features != nullptr);
+        int Bq = 0;
 
         // query chunks in registers, aligned with the row chunks this lane reads
         float qv[CPL][EPC], sc[CPL][EPC];
@@ -266,10 +270,10 @@ search_kernel(KParams p) {
             p.vis_dist[qi * (int64_t)p.vis_cap + vcount] = cdist[0];
         }
         vcount = 1;
+        const float dstart = cdist[0];
         RegPool<NCH> P;
         rp_init<NCH>(P);
         rp_insert<NCH>(P, readfirstlane64(mk_key(cdist[0], start)), Lcur, lane);
-        bool stopped = !learned && !(FULL && p.features);   // true once the decision hop has passed
         for (;;) {
             if (hops >= hcap) break;
             // Algorithm 1: expand the first unchecked pool entry
@@ -310,21 +314,24 @@ search_kernel(KParams p) {
                 wave_sync();
             }
             vcount += cnt;
-            if (LEARN && !stopped && hops >= p.s_hop) {
-                stopped = true;
-                const float d0 = key_dist(rp_get<NCH>(P, 0));
-                const float d9 = key_dist(rp_get<NCH>(P, P.size > 10 ? 9 : P.size - 1));
-                stop_features<FULL>(p, q, d0, d9, hops, xbuf, lane, qi);
-                if (learned) {
-                    chosen = stop_predict(p, xbuf, lane);
-                    hcap = chosen < hcap ? chosen : hcap;
-                }
+            if (decide && hops >= p.s_hop) {
+                // after the decision hop: features of the state, the network,
+                // the budget (once per query)
+                decide = false;
+                rp_store<NCH>(P, pool, lane);
+                wave_sync();
+                stop_decide(learn_q ? p.stop_plan : nullptr, p.s_in, p.grid_n, p.calib_c, p.s_hop, pool, P.size,
+                            dstart, ne, hops, p.features ? p.features + qi * kStopFeatures : nullptr, lane, &Bq);
+                Bq = __builtin_amdgcn_readfirstlane(Bq);
+                if (Bq > 0 && Bq < hcap) hcap = Bq;
+                wave_sync();
             }
         }
-        if (FULL && !stopped && p.features) {
-            // ended before the decision point: no features (the result is the plain one)
-            for (int t = lane; t < p.d + 3; t += 64) p.features[qi * (int64_t)(p.d + 3) + t] = NAN;
+        if (STOP && decide && p.features) {
+            // ended before the decision hop: no features
+            for (int t = lane; t < kStopFeatures; t += 64) p.features[qi * kStopFeatures + t] = NAN;
         }
+        if (STOP && p.budget && lane == 0) p.budget[qi] = Bq;
         rp_store<NCH>(P, pool, lane);
         const int size = P.size;
         wave_sync();
@@ -378,7 +385,6 @@ search_kernel(KParams p) {
             if (p.nedges) p.nedges[qi] = ne;
             if (p.vis_cnt) p.vis_cnt[qi] = vcount;
         }
-        if (LEARN && lane == 0 && p.budget) p.budget[qi] = chosen;
         wave_sync();
         if (!p.counter) break;
         unsigned int t = 0;

@@ -7,12 +7,15 @@ budget at each value of a geometric grid (16 .. 1024 expansions in 2^(1/4)
 steps); the label is log2 of the smallest budget whose top-k equals the top-k
 of the unbudgeted plain search (the plain search is the judge: the label is
 where the search has converged to its own answer, finite for every query).
-Features are taken after the 16th expansion, the same in every run, so one
-capture serves every grid point.  The network (d+3 -> 64 -> 64 -> 1, ReLU) is
-trained with the library's forward/backward and Adam kernels on z-scored
-features; the calibration constant c is the smallest one whose held-out mean
-recall meets the target when each query's budget is the grid value at or
-above c * 2^y.
+Features are 15 scalars of the suspended search after the 16th expansion
+(best distance, pool distance profile, distance to the start node, neighbour
+entries per expansion; STOP_FEATURES in the library), the same in every run,
+so one capture serves every grid point.  The network (15 -> 64 -> 64 -> 1,
+ReLU) is trained with the library's forward/backward and Adam kernels on
+z-scored features; the calibration constant c is the smallest one whose
+held-out mean recall meets the target when each query's budget is the grid
+value at or above c * 2^y.  At search time the decision is fused into the
+search loop of every query.
 """
 from __future__ import annotations
 
@@ -21,7 +24,7 @@ import dataclasses
 import numpy as np
 import torch
 
-from . import (column_stats, load_stop_model, mlp_adam, mlp_forward, mlp_forward_backward, recall_hits,
+from . import (STOP_FEATURES, column_stats, load_stop_model, mlp_adam, mlp_forward, mlp_forward_backward, recall_hits,
                search_batched, set_stop_mode)
 
 GRID = [int(round(16 * 2 ** (i / 4))) for i in range(25)]   # 16, 19, 23, ..., 1024 expansions
@@ -31,7 +34,7 @@ HIDDEN = 64
 
 @dataclasses.dataclass
 class Traces:
-    features: torch.Tensor   # [nq][d+3] float32 (NaN rows: search ended before the hop)
+    features: torch.Tensor   # [nq][STOP_FEATURES] float32 (NaN rows: search ended before the hop)
     hits: torch.Tensor       # [nq][G] int32: |top-k within budget grid[j] ∩ exact top-k|
     grid: list
     hops: torch.Tensor = None   # [nq] int64: expansions of the unbudgeted search
@@ -42,7 +45,7 @@ def traces(index, queries, truth, L, k=10, grid=GRID, chunk=50_000):
     """Plain search at pool size L under every grid budget; features at HOP."""
     nq, d = queries.shape
     dev = queries.device
-    feats = torch.empty((nq, d + 3), dtype=torch.float32, device=dev)
+    feats = torch.empty((nq, STOP_FEATURES), dtype=torch.float32, device=dev)
     hits = torch.empty((nq, len(grid)), dtype=torch.int32, device=dev)
     hops = torch.empty(nq, dtype=torch.int64, device=dev)
     same = torch.empty((nq, len(grid)), dtype=torch.int32, device=dev)

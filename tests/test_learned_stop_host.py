@@ -70,11 +70,13 @@ def test_calibrate_meets_target():
 
 def test_model_blob_layout():
     import torch
-    n_in, h = 131, 64
-    P = torch.arange(ls.HIDDEN * 0 + 12673, dtype=torch.float32)
+    n_in, h = 15, 64
+    n = n_in * h + h + h * h + h + h + 1
+    assert n == 5249
+    P = torch.arange(n, dtype=torch.float32)
     mean = torch.zeros(n_in)
     istd = torch.ones(n_in)
     b = ls.model_blob(P, mean, istd, ls.GRID)
     a = np.frombuffer(b, np.float32)
-    assert a.size == 2 * n_in + 12673 + len(ls.GRID)
-    assert a[2 * n_in] == 0 and a[2 * n_in + 12672] == 12672 and a[-1] == 1024
+    assert a.size == 2 * n_in + n + len(ls.GRID)
+    assert a[2 * n_in] == 0 and a[2 * n_in + n - 1] == n - 1 and a[-1] == 1024

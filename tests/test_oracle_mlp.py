@@ -1,18 +1,21 @@
-"""Pins of the oracle's FP64 MLP (the learned early-stop network, 131 -> 64 ->
+"""Pins of the oracle's FP64 MLP (the learned early-stop network, 15 -> 64 ->
 64 -> 1, ReLU, MSE) against central finite differences and torch FP64
-autograd, and of its Adam step against the first-step closed form."""
+autograd, of its Adam step against the first-step closed form, and of the
+early-stop features on a hand-worked search state."""
+import math
+
 import numpy as np
 import torch
 
 import oracle
 
-IN, H = 131, 64
+IN, H = 15, 64
 
 
 def _params(seed):
     rng = np.random.default_rng(seed)
     n = oracle.mlp_nparams(IN, H)
-    assert n == 131 * 64 + 64 + 64 * 64 + 64 + 64 + 1 == 12673
+    assert n == 15 * 64 + 64 + 64 * 64 + 64 + 64 + 1 == 5249
     return rng.normal(size=n) * 0.2
 
 
@@ -67,3 +70,22 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(p0 - p, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
     np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
     np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-12)
+
+
+def test_stop_features_worked_example():
+    """A pool of 12 entries with distances 3, 4, ..., 14 (ranks past the
+    pool take its last entry, 14), start node at distance 63, 50 neighbour
+    entries read over 10 expansions."""
+    f = oracle.stop_features(np.arange(3, 15, dtype=np.float32), 63.0, 50, 10)
+    assert f.shape == (15,)
+    assert f[0] == math.log(4.0)                      # ln(1 + 3)
+    assert f[1] == 3.0 / 12.0                         # d_0 / d_9 (rank 9 holds 12)
+    assert f[2] == math.log(64.0)
+    assert abs(f[3] - math.log(4.0 / 64.0)) < 1e-15
+    want = [5, 6, 8, 13, 15, 15, 15, 15, 15, 15]      # 1 + d at ranks 1, 2, 4, 9, then 14 (clamped)
+    for j, w in enumerate(want):
+        assert abs(f[4 + j] - math.log(w / 4.0)) < 1e-15, j
+    assert f[14] == 5.0
+    # degenerate: a one-entry pool at distance 0 and no expansions
+    g = oracle.stop_features(np.zeros(1, np.float32), 0.0, 0, 0)
+    assert g[1] == 1.0 and g[14] == 0.0 and (g[[0, 2, 3]] == 0).all() and (g[4:14] == 0).all()
