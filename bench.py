@@ -6,14 +6,16 @@ Pipeline (everything on the GPU through libnsg.so, outside the timed region):
   knn       exact 100-NN graph of the base (matrix-core brute force, self excluded)
   build     NSG (Algorithm 2: R=50, l=40, C=500) on the GPU
   truth     exact top-100 of the test queries (brute force)
-  sweep     plain FP32 search over L -> the smallest L with mean recall@10 >= 0.95
-  learned   per-query expansion budgets at FP16 pool sizes L16 + {0, 4, 8, 12, 16}
-            and 1.25 L16 (L16: the plain FP16 one): budget traces, labels, MLP
-            training and calibration each; the fastest on held-out training
-            queries is kept
+  sweep     plain FP32 and FP16 search over L -> the smallest L with mean
+            recall@10 >= each target (0.90, 0.95, 0.99)
+  learned   per target: per-query expansion budgets at FP16 pool sizes
+            L16 + {0, 4, 8, 12, 16} and 1.25 L16 (L16: the plain FP16 one):
+            budget traces, labels, MLP training and calibration each; the
+            fastest on held-out training queries is kept
 Timed: `--warmup` untimed steps, then `--steps` steps; a step is one search
 call over the whole 10k-query batch (queries already resident in HBM), for
-each of the two configurations.  Prints ONE JSON line.
+each configuration and target.  The headline value is FP16 + learned stop at
+recall@10 >= 0.95.  Prints ONE JSON line.
 
 The CPU baseline is the oracle's Algorithm 1 (plain C, OpenMP over queries)
 on a bounded sample of the same queries, graph and L, on the host cores.
@@ -82,6 +84,8 @@ def main():
                     help="after the timed region, copy a 1 GiB buffer twice (scales HBM byte counters)")
     ap.add_argument("--cache", default="", help="directory: reuse (or save) the graph, L and model of a "
                                                  "previous run of the same workload (profiling passes)")
+    ap.add_argument("--only-target", action="store_true",
+                    help="time the configurations of --target only (profiling passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -145,12 +149,12 @@ def main():
         h = nsg.recall_hits(ids.view(nq, 1, kk).contiguous(), truth, kk)
         return h.float().mean().item() / kk
 
-    def min_L(ix, lo=10, hi=512):
+    def min_L(ix, target, lo=10, hi=512):
         found = None
         for L in list(range(lo, 64, 2)) + list(range(64, 160, 4)) + list(range(160, hi + 1, 8)):
             ids, _ = nsg.search(ix, Qd, k, L)
             r = recall(ids)
-            if r >= args.target:
+            if r >= target:
                 found = (L, r)
                 break
         return found
@@ -167,37 +171,70 @@ def main():
         r100 = recall(ids, 100) if ids.shape[1] == 100 else None
         sweep.append(dict(L=L, r1=round(r1, 4), r10=round(r10, 4), r100=None if r100 is None else round(r100, 4)))
     log(f"sweep FP32: {sweep}")
-    f32 = min_L(ix32)
-    f16 = min_L(ix16)
-    log(f"plain FP32: L={f32}; plain FP16+rerank: L={f16}")
-    if f32 is None:
+    targets = sorted({0.90, args.target, 0.99})
+    plain = {}
+    for T in targets:
+        plain[T] = dict(f32=min_L(ix32, T), f16=min_L(ix16, T))
+        # launch shape (lanes per row, visited-filter size, waves per block,
+        # persistent grid) autotuned on the batch: results do not depend on it
+        for key, ix in (("f32", ix32), ("f16", ix16)):
+            if plain[T][key]:
+                plain[T]["launch_" + key] = nsg.autotune(ix, Qd, k, plain[T][key][0])[0]
+        log(f"recall {T}: {plain[T]}")
+    if plain[args.target]["f32"] is None:
         print(json.dumps({"error": f"plain FP32 never reaches recall@10 {args.target}"}))
         sys.exit(3)
-    L32 = f32[0]
 
-    # ---------------- learned early stop (FP16 index) ----------------
-    # The early stop gives each query an expansion budget at a fixed pool size.
-    # Pool sizes at and a little above the plain FP16 one are tried (budgets
-    # cost recall, a larger pool buys it back); each gets its own traces,
-    # network and calibration on held-out training queries, and the fastest on
-    # held-out training queries (never the test queries) is kept.
+    # ---------------- learned early stop (FP16 index), per recall target ----------------
     ntr = args.train
     Tq = torch.from_numpy(datagen.train_queries(w, ntr)).to(dev)
     ttruth, _ = nsg.knn_bruteforce(Xd, Tq, k)
+    learned = {}
+    for T in targets:
+        L_base = plain[T]["f16"][0] if plain[T]["f16"] else 512
+        best = learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, T, L_base)
+        if best is None:
+            log(f"recall {T}: the learned stop never reaches the target")
+            continue
+        learned[T] = check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, T, best)
+    if args.target not in learned:
+        print(json.dumps({"error": "the learned stop never reaches the target recall"}))
+        sys.exit(3)
+    if cache:
+        os.makedirs(args.cache, exist_ok=True)
+        arrays = {}
+        for T, m in learned.items():
+            for nm in ("P", "mean", "istd"):
+                arrays[f"{nm}_{T}"] = m[nm].cpu().numpy()
+        meta = {str(T): {a: b for a, b in m.items() if a not in ("P", "mean", "istd")} for T, m in learned.items()}
+        np.savez(cache, graph=graph.cpu().numpy(), nav=nav, rep=rep, t_knn=t_knn, t_build=t_build,
+                 plain=json.dumps({str(T): v for T, v in plain.items()}), learned=json.dumps(meta),
+                 sweep=json.dumps(sweep), **arrays)
+        log(f"saved {cache}")
+    return finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn,
+                  t_build, plain, learned, sweep)
+
+
+def learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, L_base):
+    """The early stop gives each query an expansion budget at a fixed pool
+    size.  Pool sizes at and a little above the plain FP16 one are tried
+    (budgets cost recall, a larger pool buys it back); each gets its own
+    traces, network and calibration on held-out training queries, and the
+    fastest on held-out training queries (never the test queries) is kept.
+    Also reported: a constant budget (no network) calibrated the same way."""
+    ntr = Tq.shape[0]
     n_fit = int(ntr * 0.9)
     hq = Tq[n_fit:].contiguous()
     hq_truth = ttruth[n_fit:].contiguous()
-    L_base = f16[0] if f16 else 512
     best = None
-    for L_l in sorted({L_base + dl for dl in (0, 4, 8, 12, 16)} | {int(round(L_base * 1.25))}):
-        L_l = min(L_l, 512)
+    for L_l in sorted({min(L_base + dl, 512) for dl in (0, 4, 8, 12, 16)} | {min(int(round(L_base * 1.25)), 512)}):
         t = time.time()
         tr = ls.traces(ix16, Tq, ttruth, L_l, k=k)
         torch.cuda.synchronize()
         y, reached = ls.labels(tr, k)
         hist = np.bincount(np.searchsorted(tr.grid, np.exp2(y).round()), minlength=len(tr.grid))
-        log(f"L={L_l}: traces {ntr} queries x {len(tr.grid)} budgets in {time.time() - t:.1f}s; mean expansions "
-            f"{tr.hops.float().mean().item():.1f}; converged within the grid: {reached.mean():.3f}; "
+        log(f"[{target}] L={L_l}: traces {ntr} queries x {len(tr.grid)} budgets in {time.time() - t:.1f}s; "
+            f"mean expansions {tr.hops.float().mean().item():.1f}; converged within the grid: {reached.mean():.3f}; "
             f"label histogram over {tr.grid}: {hist.tolist()}")
         t = time.time()
         P, mean, istd = ls.train(tr.features[:n_fit].contiguous(), y[:n_fit], seed=7, epochs=30, log=None)
@@ -205,77 +242,77 @@ def main():
         yh = ls.predict(P, mean, istd, tr.features[n_fit:].contiguous()).cpu().numpy()
         hold_mse = float(np.mean((yh - y[n_fit:]) ** 2))
         base_mse = float(np.mean((y[n_fit:] - y[:n_fit].mean()) ** 2))
-        cal = ls.calibrate(yh, tr.hits[n_fit:].cpu().numpy(), tr.grid, k, args.target, margin=0.003,
-                           hops=tr.hops[n_fit:].cpu().numpy())
-        log(f"L={L_l}: MLP trained in {time.time() - t:.1f}s; held-out MSE {hold_mse:.4f} (constant predictor "
-            f"{base_mse:.4f}); calibration (c, recall, mean budget, mean expansions) {cal}")
+        hits, hops = tr.hits[n_fit:].cpu().numpy(), tr.hops[n_fit:].cpu().numpy()
+        margin = min(0.003, (1.0 - target) / 10)   # held-out slack above the target
+        cal = ls.calibrate(yh, hits, tr.grid, k, target, margin=margin, hops=hops)
+        const = ls.calibrate(np.full_like(yh, y[:n_fit].mean()), hits, tr.grid, k, target, margin=margin, hops=hops)
+        log(f"[{target}] L={L_l}: MLP trained in {time.time() - t:.1f}s; held-out MSE {hold_mse:.4f} (constant "
+            f"predictor {base_mse:.4f}); calibration (c, recall, mean budget, mean expansions) {cal}; "
+            f"constant budget {const}")
         if not cal:
             continue
         ls.install(ix16, P, mean, istd, cal[0], tr.grid)
-        for hs in (1024, 2048):
-            o = dict(learned_stop=1, persistent=1, hash_slots=hs)
-            run = lambda: nsg.search_batched(ix16, hq, k_scalar=k, L_scalar=L_l, opts=o)
-            for _ in range(2):
-                run()
-            torch.cuda.synchronize()
-            t0 = time.time()
-            for _ in range(5):
-                ids, _ = run()
-            torch.cuda.synchronize()
-            ms = (time.time() - t0) / 5 * 1e3
-            hr = nsg.recall_hits(ids.view(len(hq), 1, k).contiguous(), hq_truth, k).float().mean().item() / k
-            log(f"L={L_l} hash {hs}: held-out training queries: {ms:.3f} ms per {len(hq)}, recall@10 {hr:.4f}")
-            if best is None or ms < best["ms"]:
-                best = dict(ms=ms, L=L_l, hs=hs, P=P, mean=mean, istd=istd, c=cal[0], grid=tr.grid,
-                            hold_mse=hold_mse, base_mse=base_mse, cal=cal)
-    if best is None:
-        print(json.dumps({"error": "the learned stop never reaches the target recall"}))
-        sys.exit(3)
-    L_fb, P, mean, istd, c, grid = best["L"], best["P"], best["mean"], best["istd"], best["c"], best["grid"]
-    hs_l = best["hs"]
-    hold_mse, base_mse = best["hold_mse"], best["base_mse"]
-    # test queries: recall check (c is raised if the held-out calibration falls short)
-    learned = None
+        # launch configuration (lanes per row, visited-filter size, waves per
+        # block, persistent grid) autotuned on the held-out training queries
+        tune, _ = nsg.autotune(ix16, hq, k, L_l)
+        o = dict(tune, learned_stop=1)
+        run = lambda: nsg.search_batched(ix16, hq, k_scalar=k, L_scalar=L_l, opts=o)
+        for _ in range(2):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(5):
+            ids, _ = run()
+        torch.cuda.synchronize()
+        ms = (time.time() - t0) / 5 * 1e3
+        hr = nsg.recall_hits(ids.view(len(hq), 1, k).contiguous(), hq_truth, k).float().mean().item() / k
+        log(f"[{target}] L={L_l} {tune}: held-out training queries: {ms:.3f} ms per {len(hq)}, recall@10 {hr:.4f}")
+        if best is None or ms < best["ms"]:
+            best = dict(ms=ms, L=L_l, launch=tune, P=P, mean=mean, istd=istd, c=cal[0], grid=list(tr.grid),
+                        heldout_mse=hold_mse, const_mse=base_mse, heldout_calibration=cal,
+                        constant_budget_calibration=const)
+    return best
+
+
+def check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, target, best):
+    """Recall of the chosen model on the test queries (c is raised on the
+    2^(1/4) ladder if the held-out calibration falls short)."""
+    nq = Qd.shape[0]
+    c = best["c"]
     for _ in range(12):
-        ls.install(ix16, P, mean, istd, c, grid)
+        ls.install(ix16, best["P"], best["mean"], best["istd"], c, best["grid"])
         Bu = torch.empty(nq, dtype=torch.int32, device=dev)
         hq_h = torch.empty(nq, dtype=torch.int64, device=dev)
-        ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L_fb,
-                                    opts=dict(learned_stop=1, budget=Bu, hops=hq_h, persistent=1, hash_slots=hs_l))
-        r = recall(ids)
-        learned = dict(L=L_fb, hash_slots=hs_l, c=c, recall=r, mean_budget=float(Bu.float().mean().item()),
-                       mean_expansions=float(hq_h.float().mean().item()), heldout_calibration=best["cal"])
-        if r >= args.target:
+        ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=best["L"],
+                                    opts=dict(best["launch"], learned_stop=1, budget=Bu, hops=hq_h))
+        r = nsg.recall_hits(ids.view(nq, 1, k).contiguous(), truth, k).float().mean().item() / k
+        if r >= target:
             break
         c *= 2 ** 0.25
-    log(f"learned stop on the test queries: {learned}")
-    if cache:
-        os.makedirs(args.cache, exist_ok=True)
-        np.savez(cache, graph=graph.cpu().numpy(), nav=nav, rep=rep, t_knn=t_knn, t_build=t_build, L32=L32,
-                 grid=np.asarray(grid),
-                 L_fb=L_fb, c=c, P=P.cpu().numpy(), mean=mean.cpu().numpy(), istd=istd.cpu().numpy(),
-                 f16=np.asarray(f16 if f16 else (0, 0.0)), hold_mse=hold_mse, base_mse=base_mse,
-                 sweep=json.dumps(sweep), learned=json.dumps(learned))
-        log(f"saved {cache}")
-    return finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn,
-                  t_build, L32, L_fb, f16, learned, hold_mse, base_mse, sweep)
+    out = {a: b for a, b in best.items() if a != "ms"}
+    out.update(c=c, recall=r, mean_budget=float(Bu.float().mean().item()),
+               mean_expansions=float(hq_h.float().mean().item()))
+    log(f"[{target}] learned stop on the test queries: "
+        f"{ {a: b for a, b in out.items() if a not in ('P', 'mean', 'istd', 'grid')} }")
+    return out
 
 
 def run_timed(args, z, nsg, ls, torch, dev, w, X, Q, Xd, Qd, ix32, ix16, graph, nav, rep, deg, truth, k,
               t_knn, t_build):
-    """Timed part only, with L, model and calibration from a cached run."""
-    P = torch.from_numpy(z["P"]).to(dev)
-    mean = torch.from_numpy(z["mean"]).to(dev)
-    istd = torch.from_numpy(z["istd"]).to(dev)
-    ls.install(ix16, P, mean, istd, float(z["c"]), [int(g) for g in z["grid"]])
-    f16 = tuple(z["f16"].tolist()) if z["f16"][0] else None
-    return finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn,
-                  t_build, int(z["L32"]), int(z["L_fb"]), f16, json.loads(str(z["learned"])),
-                  float(z["hold_mse"]), float(z["base_mse"]), json.loads(str(z["sweep"])))
+    """Timed part only, with L, models and calibrations from a cached run."""
+    plain = {float(T): v for T, v in json.loads(str(z["plain"])).items()}
+    learned = {}
+    for T, m in json.loads(str(z["learned"])).items():
+        m = dict(m)
+        for nm in ("P", "mean", "istd"):
+            m[nm] = torch.from_numpy(z[f"{nm}_{float(T)}"]).to(dev)
+        learned[float(T)] = m
+    return finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn,
+                  t_build, plain, learned, json.loads(str(z["sweep"])))
 
 
-def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn, t_build,
-           L32, L_fb, f16, learned, hold_mse, base_mse, sweep):
+def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn, t_build,
+           plain, learned, sweep):
     nq = Q.shape[0]
 
     def recall(ids, kk=k):
@@ -298,42 +335,60 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
         ms = [a.elapsed_time(b) for a, b in ev]
         return float(np.mean(ms)), wall
 
-    out32 = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), device=dev))
+    out = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), device=dev))
     hops = torch.empty(nq, dtype=torch.int64, device=dev)
     ndist = torch.empty(nq, dtype=torch.int64, device=dev)
     nedge = torch.empty(nq, dtype=torch.int64, device=dev)
+    # warm the clocks before the first timed configuration
+    L32 = plain[args.target]["f32"][0]
+    launch32 = plain[args.target]["launch_f32"]
+    for _ in range(30):
+        nsg.search_batched(ix32, Qd, k_scalar=k, L_scalar=L32, out_ids=out[0], out_dist=out[1], opts=launch32)
+    torch.cuda.synchronize()
 
-    def step32():
-        nsg.search(ix32, Qd, k, L32, out_ids=out32[0], out_dist=out32[1])
-
-    ms32, wall32 = timed(step32, args.steps, args.warmup)
-    r32 = recall(out32[0])
-    out16 = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), device=dev))
-
-    def step16():
-        nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L_fb, out_ids=out16[0], out_dist=out16[1],
-                           opts=dict(learned_stop=1, persistent=1, hash_slots=int((learned or {}).get("hash_slots", 0))))
-
-    ms16, wall16 = timed(step16, args.steps, args.warmup)
-    r16 = recall(out16[0])
-    out16p = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), device=dev))
-    ms16p = None
-    if f16:
-        def step16p():
-            nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=int(f16[0]), out_ids=out16p[0], out_dist=out16p[1],
-                               opts=dict(persistent=1))
-        ms16p, _ = timed(step16p, args.steps, args.warmup)
-        log(f"plain FP16 (+FP32 re-rank) L={f16[0]}: {ms16p:.3f} ms/step, recall@10 {recall(out16p[0]):.4f}")
-    qps32 = nq / (ms32 / 1e3)
-    qps16 = nq / (ms16 / 1e3)
+    per_target = {}
+    for T in sorted(plain):
+        if args.only_target and T != args.target:
+            continue
+        row = {}
+        for name, key, ix in (("plain_fp32", "f32", ix32), ("plain_fp16", "f16", ix16)):
+            f = plain[T][key]
+            if not f:
+                continue
+            L, tune = f[0], plain[T]["launch_" + key]
+            ms, _ = timed(lambda: nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, out_ids=out[0], out_dist=out[1],
+                                                     opts=tune), args.steps, args.warmup)
+            row[name] = dict(L=L, ms=round(ms, 4), qps=round(nq / ms * 1e3, 1), recall10=round(recall(out[0]), 4),
+                             launch=tune)
+        m = learned.get(T)
+        if m:
+            ls.install(ix16, m["P"], m["mean"], m["istd"], m["c"], m["grid"])
+            o = dict(m["launch"], learned_stop=1)
+            ms, _ = timed(lambda: nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=int(m["L"]), out_ids=out[0],
+                                                     out_dist=out[1], opts=o), args.steps, args.warmup)
+            row["fp16_learned"] = dict(ms=round(ms, 4), qps=round(nq / ms * 1e3, 1), recall10=round(recall(out[0]), 4),
+                                       **{a: b for a, b in m.items() if a not in ("P", "mean", "istd", "grid")})
+        log(f"recall {T}: {row}")
+        per_target[T] = row
+    head = per_target[args.target]
+    if "fp16_learned" not in head or "plain_fp32" not in head:
+        print(json.dumps({"error": "no timed learned-stop or plain FP32 result at the target recall"}))
+        sys.exit(3)
+    qps16, ms16, r16 = head["fp16_learned"]["qps"], head["fp16_learned"]["ms"], head["fp16_learned"]["recall10"]
+    qps32, ms32, r32 = head["plain_fp32"]["qps"], head["plain_fp32"]["ms"], head["plain_fp32"]["recall10"]
     log(f"plain FP32 L={L32}: {ms32:.3f} ms/step, {qps32:,.0f} QPS, recall@10 {r32:.4f}")
     log(f"FP16 + learned stop: {ms16:.3f} ms/step, {qps16:,.0f} QPS, recall@10 {r16:.4f}")
+    # the plain FP32 step again, for the roofline
+    ms32, _ = timed(lambda: nsg.search_batched(ix32, Qd, k_scalar=k, L_scalar=L32, out_ids=out[0], out_dist=out[1],
+                                               opts=launch32), args.steps, args.warmup)
+    out32 = out
 
     # ---------------- roofline of the dominant kernel (plain FP32 search) ----------------
     # counts with a visited filter large enough never to forget (= the
     # oracle's exact visited set), so only the method's own bytes are credited
     nsg.search_batched(ix32, Qd, k_scalar=k, L_scalar=L32,
                        opts=dict(hops=hops, ndist=ndist, nedges=nedge, hash_slots=16384))
+    lpr32 = int(launch32["lanes_per_row"]) or 8
     torch.cuda.synchronize()
     d = X.shape[1]
     H, N, E = hops.sum().item(), ndist.sum().item(), nedge.sum().item()
@@ -341,7 +396,8 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
     achieved = alg_bytes / (ms32 / 1e3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=8000.0, unit="GB/s",
                 frac=round(achieved / 8000.0, 4), traffic=measured_traffic(),
-                kernel="search_kernel<F32, lanes per row 8, chunks per lane 4, plain, 2 pool chunks>",
+                kernel=f"search_kernel<F32, lanes per row {lpr32}, chunks per lane {-(-32 // lpr32)}, plain, "
+                       f"2 pool chunks>", launch=launch32,
                 bytes_per_launch=int(alg_bytes),
                 per_query=dict(hops=H / nq, ndist=N / nq, edges=E / nq))
     log(f"roofline: {roof}")
@@ -374,14 +430,15 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
                           f"same graph; {el:.1f}s; GPU id sets equal on {same * 100:.1f}%")
         log(f"cpu baseline: {cpu}")
 
+    d = X.shape[1]
     res = {
         "metric": "QPS at recall@10>=0.95, 1M x 128: FP16 storage + learned early stop (vs plain FP32)",
-        "value": round(qps16, 1),
+        "value": qps16,
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms16, 4),
+        "ms_per_step": ms16,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -390,14 +447,13 @@ def finish(args, nsg, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg,
         "config": {
             "workload": f"{w.name}: {X.shape[0]} x {d} float32 latent Gaussian mixture, {nq} queries, "
                         f"NSG R={w.R} l={w.Lb} C={w.C} from exact {w.K}-NN graph; k={k}",
-            "plain_fp32": dict(L=L32, qps=round(qps32, 1), ms_per_step=round(ms32, 4), recall10=round(r32, 4)),
-            "fp16_learned": dict(qps=round(qps16, 1), recall10=round(r16, 4), **(learned or {})),
-            "plain_fp16_ms_per_step": None if ms16p is None else round(ms16p, 4),
-            "plain_fp16_L": f16,
+            "plain_fp32": head["plain_fp32"],
+            "fp16_learned": head["fp16_learned"],
+            "plain_fp16": head.get("plain_fp16"),
             "speedup_vs_plain_fp32": round(qps16 / qps32, 3),
+            "by_recall_target": {str(T): v for T, v in per_target.items()},
             "index": dict(nav=nav, repair_edges=rep, aod=round(deg.mean().item(), 2), mod=int(deg.max().item()),
                           knn_s=round(t_knn, 2), build_s=round(t_build, 2)),
-            "mlp": dict(heldout_mse=round(hold_mse, 4), const_mse=round(base_mse, 4)),
             "sweep_fp32": sweep,
         },
         "roofline": roof,

@@ -127,8 +127,11 @@ const int64_t kPersistentMinBatch = 4096;
 // a query visits roughly 25 nodes per pool entry; size the filter to that
 // (it forgets beyond, which only costs recomputation)
 int default_hash_bits(int L) {
+    // 24 L slots, within [1024, 2048]: a larger filter forgets fewer nodes
+    // (fewer repeated distance evaluations) but its LDS lowers the number of
+    // resident wavefronts, which costs more at every pool size measured
     int want = L * 24, bits = 10;
-    while ((1 << bits) < want && bits < 13) ++bits;
+    while ((1 << bits) < want && bits < 11) ++bits;
     return bits;
 }
 
@@ -533,7 +536,6 @@ extern "C" int nsg_autotune(const nsg_index *idx, const float *queries, int64_t 
         if (c > 4 || (lprs[li] / 2 >= idx->row_chunks && lprs[li] != lpr0))
             continue;   // too few lanes for the row, or half of them idle
         for (int hi = 0; hi < 3 && rc == NSG_OK; ++hi) {
-            if (hashes[hi] < 8 * L && hi < 2) continue;
             for (int wi = 0; wi < 3 && rc == NSG_OK; ++wi)
                 for (int pers = 0; pers < 2 && rc == NSG_OK; ++pers) {
                     nsg_search_opts o{};

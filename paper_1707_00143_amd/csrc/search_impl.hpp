@@ -194,7 +194,7 @@ __device__ __attribute__((noinline)) int stop_decide(const float *plan, int in, 
 // NCH: pool chunks of 64 held in registers (NCH * 64 >= L_alloc).
 // Occupancy targets for the common 2-chunk pool: the plain search at 5 waves
 // per SIMD (<= 96 registers; a few cold values go to scratch, measured
-// faster), the learned-stop variant at 4.
+// faster), the learned-stop variant too.
 template <int DT, int LPR, int CPL, int MODE, int NCH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 2 ? (MODE <= 1 ? 5 : 1) : 1)))
 search_kernel(KParams p) {

@@ -206,3 +206,37 @@ def test_max_hops_matches_oracle(nsg, tiny_index):
         r = compare(X, Q, _np(ids).view(np.uint32), _np(dist), o_ids)
         assert r["ok"], (B, r)
     ix.close()
+
+
+def test_trained_network_beats_constant_budget(nsg, tiny_index):
+    """What the trained network gains over the method without it: on the tiny
+    index, budgets from the network trained on the plain search's own traces
+    reach a held-out recall target (one point below the unbudgeted search's)
+    with fewer expansions than one constant budget calibrated the same way,
+    and the network's held-out error is below the constant predictor's."""
+    dev = _dev()
+    import datagen
+    from paper_1707_00143_amd import learned_stop as ls
+    X, G, nav = tiny_index["X"], tiny_index["graph"], tiny_index["nav"]
+    ix = nsg.load_index(torch.from_numpy(X).to(dev), torch.from_numpy(G.view(np.int32)).to(dev), nav, "f32")
+    Xd = torch.from_numpy(X).to(dev)
+    Tq = torch.from_numpy(datagen.train_queries(tiny_index["w"], 20_000)).to(dev)
+    truth, _ = nsg.knn_bruteforce(Xd, Tq, 10)
+    L, k = 60, 10
+    tr = ls.traces(ix, Tq, truth, L, k=k)
+    y, _ = ls.labels(tr, k)
+    n_fit = 18_000
+    P, mean, istd = ls.train(tr.features[:n_fit].contiguous(), y[:n_fit], seed=3, epochs=30)
+    yh = _np(ls.predict(P, mean, istd, tr.features[n_fit:].contiguous()))
+    hits, hops = _np(tr.hits[n_fit:]), _np(tr.hops[n_fit:])
+    mse = float(np.mean((yh - y[n_fit:]) ** 2))
+    mse0 = float(np.mean((y[n_fit:] - y[:n_fit].mean()) ** 2))
+    target = hits[:, -1].mean() / k - 0.01        # one point below the unbudgeted search
+    net = ls.calibrate(yh, hits, tr.grid, k, target, hops=hops)
+    const = ls.calibrate(np.full_like(yh, y[:n_fit].mean()), hits, tr.grid, k, target, hops=hops)
+    print(f"target {target:.4f}: held-out MSE {mse:.4f} vs constant {mse0:.4f}; network {net}; "
+          f"constant budget {const}; unbudgeted expansions {hops.mean():.1f}")
+    assert mse < mse0
+    assert net is not None and const is not None
+    assert net[3] < const[3], (net, const)       # mean expansions at the same recall target
+    ix.close()
