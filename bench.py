@@ -192,7 +192,7 @@ def main():
     learned = {}
     for T in targets:
         L_base = plain[T]["f16"][0] if plain[T]["f16"] else 512
-        best = learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, T, L_base)
+        best = learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, T, L_base, nq)
         if best is None:
             log(f"recall {T}: the learned stop never reaches the target")
             continue
@@ -215,7 +215,7 @@ def main():
                   t_build, plain, learned, sweep)
 
 
-def learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, L_base):
+def learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, L_base, nq_test):
     """The early stop gives each query an expansion budget at a fixed pool
     size.  Pool sizes at and a little above the plain FP16 one are tried
     (budgets cost recall, a larger pool buys it back); each gets its own
@@ -253,10 +253,12 @@ def learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, L_base):
             continue
         ls.install(ix16, P, mean, istd, cal[0], tr.grid)
         # launch configuration (lanes per row, visited-filter size, waves per
-        # block, persistent grid) autotuned on the held-out training queries
-        tune, _ = nsg.autotune(ix16, hq, k, L_l)
+        # block, persistent grid) of the learned search, autotuned on a batch
+        # of held-out training queries as large as the test batch
+        hb = hq[:nq_test].contiguous()
+        tune, _ = nsg.autotune(ix16, hb, k, L_l, learned_stop=1)
         o = dict(tune, learned_stop=1)
-        run = lambda: nsg.search_batched(ix16, hq, k_scalar=k, L_scalar=L_l, opts=o)
+        run = lambda: nsg.search_batched(ix16, hb, k_scalar=k, L_scalar=L_l, opts=o)
         for _ in range(2):
             run()
         torch.cuda.synchronize()
@@ -265,8 +267,9 @@ def learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, L_base):
             ids, _ = run()
         torch.cuda.synchronize()
         ms = (time.time() - t0) / 5 * 1e3
-        hr = nsg.recall_hits(ids.view(len(hq), 1, k).contiguous(), hq_truth, k).float().mean().item() / k
-        log(f"[{target}] L={L_l} {tune}: held-out training queries: {ms:.3f} ms per {len(hq)}, recall@10 {hr:.4f}")
+        hr = nsg.recall_hits(ids.view(len(hb), 1, k).contiguous(), hq_truth[:len(hb)].contiguous(),
+                             k).float().mean().item() / k
+        log(f"[{target}] L={L_l} {tune}: held-out training queries: {ms:.3f} ms per {len(hb)}, recall@10 {hr:.4f}")
         if best is None or ms < best["ms"]:
             best = dict(ms=ms, L=L_l, launch=tune, P=P, mean=mean, istd=istd, c=cal[0], grid=list(tr.grid),
                         heldout_mse=hold_mse, const_mse=base_mse, heldout_calibration=cal,

@@ -154,8 +154,7 @@ typedef struct nsg_search_graph nsg_search_graph;   /* opaque, owned by the libr
  * Capture one nsg_search_batched call (same arguments) into a HIP graph and
  * instantiate it.  The buffers are bound at capture: refill `queries` (and
  * k / L) in place, then nsg_search_graph_launch replays the whole batch with
- * one launch.  With opts->persistent the graph owns its work counter; with
- * early-stop features or the learned stop it owns the two-phase scratch.
+ * one launch.  With opts->persistent the graph owns its work counter.
  */
 int nsg_search_graph_create(const nsg_index *idx, const float *queries, int64_t nq,
                             const int32_t *k, const int32_t *L, int32_t k_scalar,
@@ -169,9 +168,10 @@ void nsg_search_graph_destroy(nsg_search_graph *g);   /* NULL-safe; synchronises
  * Time candidate launch configurations of nsg_search_batched (lanes per row,
  * waves per block, visited-filter size, persistent grid) on the given batch
  * (scalar k, L) and return the fastest in *best (host; other fields zeroed)
- * with its mean time per call in *best_ms (host).  `trials` timed calls per
- * candidate after one warm-up.  Synchronous; writes no caller memory except
- * *best and *best_ms.
+ * with its mean time per call in *best_ms (host).  On input, best->learned_stop
+ * is honoured (every candidate is timed with it; the other input fields are
+ * ignored).  `trials` timed calls per candidate after one warm-up.
+ * Synchronous; writes no caller memory except *best and *best_ms.
  */
 int nsg_autotune(const nsg_index *idx, const float *queries, int64_t nq, int32_t k,
                  int32_t L, int32_t trials, nsg_search_opts *best, float *best_ms,

@@ -338,9 +338,10 @@ class SearchGraph:
             pass
 
 
-def autotune(index, queries, k, L, trials=3, stream=None):
+def autotune(index, queries, k, L, trials=3, learned_stop=0, stream=None):
     """nsg_autotune: returns (opts dict for search_batched, ms per call)."""
     o = SearchOpts()
+    o.learned_stop = int(learned_stop)
     ms = ctypes.c_float()
     _call("nsg_autotune", index.handle, _dev(queries, torch.float32, "queries"), queries.shape[0], int(k), int(L),
           int(trials), ctypes.byref(o), ctypes.byref(ms), _stream(stream))

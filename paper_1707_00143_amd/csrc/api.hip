@@ -525,6 +525,7 @@ extern "C" int nsg_autotune(const nsg_index *idx, const float *queries, int64_t 
     }
     int lpr0, cpl0;
     pick_layout(idx->row_chunks, 4, &lpr0, &cpl0);
+    const int learned = best->learned_stop;   // the one input field of *best
     const int lprs[4] = {8, 16, 32, 64};
     const int hashes[3] = {1024, 2048, 4096};
     const int wpbs[3] = {1, 2, 4};
@@ -543,6 +544,7 @@ extern "C" int nsg_autotune(const nsg_index *idx, const float *queries, int64_t 
                     o.hash_slots = hashes[hi];
                     o.waves_per_block = wpbs[wi];
                     o.persistent = pers;
+                    o.learned_stop = learned;
                     o.counter = ctr;
                     int r = nsg_search_batched(idx, queries, nq, nullptr, nullptr, k, L, k, ids, dist, &o, stream);
                     if (r == NSG_EUNSUPPORTED) { clear_error(); continue; }

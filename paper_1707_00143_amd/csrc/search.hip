@@ -117,7 +117,9 @@ int launch_search(const SearchArgs &a) {
     }
     const bool full = a.vis_ids || a.pool_ids || a.hops || a.ndist || a.nedges || a.self_offset >= 0;
     const int mode = full ? 2 : (a.learned || a.features || a.budget) ? 1 : 0;
-    const int nch = L_alloc <= 128 ? 2 : L_alloc <= 256 ? 4 : 8;   // pool registers per lane: 2 * nch
+    // pool chunks of 64 held in registers (2 * nch registers per lane); the
+    // LDS copy of the pool (re-rank sort) keeps the power-of-two L_alloc
+    const int nch = a.L_cap <= 128 ? 2 : a.L_cap <= 256 ? 4 : a.L_cap <= 384 ? 6 : 8;
     kfn_t fn = nullptr;
     switch (ix->storage) {
     case NSG_F32: fn = mode == 2 ? pick_search_kernel_f32_full(lpr, cpl, nch)

@@ -191,7 +191,7 @@ __device__ __attribute__((noinline)) int stop_decide(const float *plan, int in, 
 // learned early stop and the feature capture at the decision hop; 2 every
 // option (visited recording, pool output, counters, own-row visit).  Options
 // left out keep registers free for occupancy.
-// NCH: pool chunks of 64 held in registers (NCH * 64 >= L_alloc).
+// NCH: pool chunks of 64 held in registers (NCH * 64 >= the pool capacity).
 // Occupancy targets for the common 2-chunk pool: the plain search at 5 waves
 // per SIMD (<= 96 registers; a few cold values go to scratch, measured
 // faster), the learned-stop variant too.
@@ -397,14 +397,16 @@ search_kernel(KParams p) {
 typedef void (*kfn_t)(KParams);
 
 // Kernel for a layout (lanes per row, chunks per lane), a MODE and nch pool
-// chunks of 64 held in registers (2, 4 or 8: pool capacity <= 128, 256, 512).
+// chunks of 64 held in registers (2, 4, 6 or 8: pool capacity <= 128, 256,
+// 384, 512).
 // Each per-format source instantiates one MODE.
 template <int DT, int MODE>
 static kfn_t pick_kernel_t(int lpr, int cpl, int nch) {
 #define NSG_K(L_, C_)                                                                   \
     if (lpr == L_ && cpl == C_)                                                         \
         return nch <= 2 ? search_kernel<DT, L_, C_, MODE, 2>                          \
-                        : nch <= 4 ? search_kernel<DT, L_, C_, MODE, 4> : search_kernel<DT, L_, C_, MODE, 8>;
+                        : nch <= 4 ? search_kernel<DT, L_, C_, MODE, 4>                 \
+                        : nch <= 6 ? search_kernel<DT, L_, C_, MODE, 6> : search_kernel<DT, L_, C_, MODE, 8>;
     NSG_K(8, 1) NSG_K(8, 2) NSG_K(8, 4)
     NSG_K(16, 1) NSG_K(16, 2) NSG_K(16, 4)
     NSG_K(32, 1) NSG_K(32, 2) NSG_K(32, 4)

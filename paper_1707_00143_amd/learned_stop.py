@@ -7,7 +7,7 @@ budget at each value of a geometric grid (16 .. 1024 expansions in 2^(1/4)
 steps); the label is log2 of the smallest budget whose top-k equals the top-k
 of the unbudgeted plain search (the plain search is the judge: the label is
 where the search has converged to its own answer, finite for every query).
-Features are 15 scalars of the suspended search after the 16th expansion
+Features are 15 scalars of the search state after the 16th expansion
 (best distance, pool distance profile, distance to the start node, neighbour
 entries per expansion; STOP_FEATURES in the library), the same in every run,
 so one capture serves every grid point.  The network (15 -> 64 -> 64 -> 1,
