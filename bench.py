@@ -9,7 +9,8 @@ Pipeline (everything on the GPU through libnsg.so, outside the timed region):
   sweep     plain FP32 and FP16 search over L -> the smallest L with mean
             recall@10 >= each target (0.90, 0.95, 0.99)
   learned   per target: per-query expansion budgets at FP16 pool sizes
-            L16 + {0, 4, 8, 12, 16} and 1.25 L16 (L16: the plain FP16 one):
+            L16 + {0, 4, 8, 12, 16}, 1.125 L16, 1.25 L16 and the register-chunk
+            boundary (128, 256, 384) below 1.5 L16 (L16: the plain FP16 one):
             budget traces, labels, MLP training and calibration each; the
             fastest on held-out training queries is kept
 Timed: `--warmup` untimed steps, then `--steps` steps; a step is one search
@@ -227,7 +228,10 @@ def learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, L_base, nq_tes
     hq = Tq[n_fit:].contiguous()
     hq_truth = ttruth[n_fit:].contiguous()
     best = None
-    for L_l in sorted({min(L_base + dl, 512) for dl in (0, 4, 8, 12, 16)} | {min(int(round(L_base * 1.25)), 512)}):
+    cands = {L_base + dl for dl in (0, 4, 8, 12, 16)} | {int(round(L_base * f)) for f in (1.125, 1.25)}
+    # the largest pool held in the same number of 64-entry register chunks
+    cands |= {c for c in (128, 256, 384) if L_base < c <= 1.5 * L_base}
+    for L_l in sorted({min(c, 512) for c in cands}):
         t = time.time()
         tr = ls.traces(ix16, Tq, ttruth, L_l, k=k)
         torch.cuda.synchronize()

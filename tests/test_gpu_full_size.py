@@ -1,0 +1,112 @@
+"""GPU parity at the benchmark's full size: the SIFT-like 1M x 128 workload,
+10,000 queries, the graph built on the GPU (exact 100-NN graph, Algorithm 2
+with R=50, l=40, C=500), searched in the launch configurations the benchmark
+times (the default persistent launch and the autotuned one).  The oracle's
+Algorithm 1 runs on a sample of the queries over the same graph; properties
+that hold at any size are checked on every query."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SAMPLE = slice(0, None, 40)   # 250 of the 10,000 test queries
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_00143_amd as nsg
+    dev = torch.device("cuda:0")
+    w = datagen.SIFT1M_LIKE
+    X = datagen.base(w)
+    Q = datagen.queries(w)
+    print(f"full-size fixture: {w.name}, base {X.shape}, queries {Q.shape}", flush=True)
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
+    graph, nav, _ = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
+    del knn
+    torch.cuda.synchronize()
+    G = _np(graph).view(np.uint32)
+    yield dict(nsg=nsg, X=X, Q=Q, Xd=Xd, Qd=Qd, graph=graph, G=G, nav=nav)
+
+
+def _properties(ids, dist):
+    """Every row sorted by (distance, id), no repeated id, padding last."""
+    ids = ids.astype(np.int64)
+    for i in range(ids.shape[0]):
+        row = ids[i][ids[i] != 0xFFFFFFFF]
+        d = dist[i][:len(row)]
+        assert len(set(row.tolist())) == len(row), i
+        keys = list(zip(d.tolist(), row.tolist()))
+        assert keys == sorted(keys), i
+
+
+@pytest.mark.parametrize("launch", ["default", "autotuned"])
+def test_full_size_fp32_sampled_parity(full, launch):
+    nsg, X, Q, G, nav = full["nsg"], full["X"], full["Q"], full["G"], full["nav"]
+    ix = nsg.load_index(full["Xd"], full["graph"], nav, "f32")
+    k, L = 10, 84
+    if launch == "default":
+        ids, dist = nsg.search(ix, full["Qd"], k, L)
+    else:
+        opts, _ = nsg.autotune(ix, full["Qd"], k, L)
+        ids, dist = nsg.search_batched(ix, full["Qd"], k_scalar=k, L_scalar=L, opts=opts)
+    ids, dist = _np(ids).view(np.uint32), _np(dist)
+    _properties(ids, dist)
+    o_ids, _, _, _ = oracle.search(X, G, nav, Q[SAMPLE], k, L, threads=16)
+    r = compare(X, Q[SAMPLE], ids[SAMPLE], dist[SAMPLE], o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    ix.close()
+
+
+def test_full_size_fp32_k100_large_pool(full):
+    """k = 100 at L = 300 (the sweep's large end), sampled."""
+    nsg, X, Q, G, nav = full["nsg"], full["X"], full["Q"], full["G"], full["nav"]
+    ix = nsg.load_index(full["Xd"], full["graph"], nav, "f32")
+    ids, dist = nsg.search(ix, full["Qd"], 100, 300)
+    ids, dist = _np(ids).view(np.uint32), _np(dist)
+    _properties(ids, dist)
+    s = slice(0, None, 160)
+    o_ids, _, _, _ = oracle.search(X, G, nav, Q[s], 100, 300, threads=16)
+    r = compare(X, Q[s], ids[s], dist[s], o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    ix.close()
+
+
+def test_full_size_fp16_sampled_parity(full):
+    """FP16 storage: the walk equals the oracle's Algorithm 1 over the
+    oracle's decoded rows; the re-ranked output equals the oracle's exact FP32
+    re-rank of that pool."""
+    nsg, X, Q, G, nav = full["nsg"], full["X"], full["Q"], full["G"], full["nav"]
+    ix = nsg.load_index(full["Xd"], full["graph"], nav, "f16")
+    k, L = 10, 84
+    nq = Q.shape[0]
+    dev = full["Qd"].device
+    pids = torch.empty((nq, L), dtype=torch.int32, device=dev)
+    pd = torch.empty((nq, L), dtype=torch.float32, device=dev)
+    walk_ids, walk_d = nsg.search_batched(ix, full["Qd"], k_scalar=k, L_scalar=L,
+                                          opts=dict(rerank=-1, pool_ids=pids, pool_dist=pd, pool_stride=L))
+    opts, _ = nsg.autotune(ix, full["Qd"], k, L)
+    ids, dist = nsg.search_batched(ix, full["Qd"], k_scalar=k, L_scalar=L, opts=opts)
+    ids, dist = _np(ids).view(np.uint32), _np(dist)
+    _properties(ids, dist)
+    _, Xt = oracle.quantize("f16", X, oracle.scales("f16", X))
+    o_ids, _, _, _, o_pids, _ = oracle.search(Xt, G, nav, Q[SAMPLE], k, L, pool_stride=L, threads=16)
+    r = compare(Xt, Q[SAMPLE], _np(walk_ids).view(np.uint32)[SAMPLE], _np(walk_d)[SAMPLE], o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    rr_ids, _ = oracle.rerank(X, Q[SAMPLE], o_pids, k)
+    r = compare(X, Q[SAMPLE], ids[SAMPLE], dist[SAMPLE], rr_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    ix.close()
