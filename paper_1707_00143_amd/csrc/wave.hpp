@@ -54,14 +54,21 @@ __device__ inline float e4m3_to_f32(uint32_t b) {
     v = (e == 15u && m == 7u) ? __uint_as_float(0x7FC00000u) : v;
     return __uint_as_float(__float_as_uint(v) | s);
 }
+// The packed hardware conversion decodes OCP E4M3 exactly as e4m3_to_f32
+// does (checked on all 256 codes on gfx950), two bytes per instruction.
 template <> struct Fmt<NSG_E4M3> {
     static constexpr int EPC = 16;
     __device__ static inline void dec(const uint4 r, float *o) {
         const uint32_t w[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) o[4 * i + j] = e4m3_to_f32((w[i] >> (8 * j)) & 0xFFu);
+        for (int i = 0; i < 4; ++i) {
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);   // bytes 0, 1
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);    // bytes 2, 3
+            o[4 * i] = lo[0];
+            o[4 * i + 1] = lo[1];
+            o[4 * i + 2] = hi[0];
+            o[4 * i + 3] = hi[1];
+        }
     }
 };
 
