@@ -240,3 +240,30 @@ def test_trained_network_beats_constant_budget(nsg, tiny_index):
     assert net is not None and const is not None
     assert net[3] < const[3], (net, const)       # mean expansions at the same recall target
     ix.close()
+
+
+def test_e4m3_decode_every_finite_code(nsg):
+    """The search decodes every finite E4M3 code exactly as the oracle's field
+    decode: row c holds the value of code c in all 16 dimensions (scale 1,
+    since every column's largest magnitude is 448), the graph is a ring, the
+    pool covers every row, and the distance to the zero query is exactly
+    16 * v_c^2 (E4M3 squares are exact in FP32)."""
+    dev = _dev()
+    codes = np.array([c for c in range(256) if c not in (0x7F, 0xFF)], np.uint8)
+    v = oracle.decode("e4m3", codes)
+    n, d = len(codes), 16
+    X = np.repeat(v[:, None], d, axis=1).astype(np.float32)
+    assert np.abs(X).max(0).min() == 448.0
+    G = np.stack([(np.arange(n) + 1) % n, (np.arange(n) - 1) % n], 1).astype(np.uint32)
+    ix = nsg.load_index(torch.from_numpy(X).to(dev), torch.from_numpy(G.view(np.int32)).to(dev), 0, "e4m3")
+    L = 256
+    q = torch.zeros((1, d), dtype=torch.float32, device=dev)
+    pids = torch.empty((1, L), dtype=torch.int32, device=dev)
+    pd = torch.empty((1, L), dtype=torch.float32, device=dev)
+    nsg.search_batched(ix, q, k_scalar=1, L_scalar=L, opts=dict(rerank=-1, pool_ids=pids, pool_dist=pd, pool_stride=L))
+    ids, dist = _np(pids)[0].view(np.uint32), _np(pd)[0]
+    got = {int(i): float(x) for i, x in zip(ids, dist) if int(i) != 0xFFFFFFFF}
+    assert len(got) == n
+    want = 16.0 * v.astype(np.float64) ** 2
+    assert all(got[c] == want[c] for c in range(n))
+    ix.close()
