@@ -73,7 +73,8 @@ def test_search_edge_cases(tiny_gpu, nsg):
     r = compare(t["X"], Q[:7], ids, _np(dist), o_ids)
     assert r["ok"], r
     # L = 1, k = 1 (greedy walk) and a ragged batch (not a multiple of the block)
-    for (k, L, nq) in [(1, 1, 13), (1, 512, 5), (100, 100, 33)]:
+    # pools of 2, 4, 6 and 8 register chunks
+    for (k, L, nq) in [(1, 1, 13), (1, 512, 5), (100, 100, 33), (10, 200, 9), (10, 300, 9)]:
         ids, dist = nsg.search(t["ix"], Qd[:nq], k, L)
         o_ids, _, _, _ = oracle.search(t["X"], t["graph"], t["nav"], Q[:nq], k, L)
         r = compare(t["X"], Q[:nq], _np(ids).view(np.uint32), _np(dist), o_ids)
