@@ -1,9 +1,11 @@
-"""GPU parity at the benchmark's full size: the SIFT-like 1M x 128 workload,
-10,000 queries, the graph built on the GPU (exact 100-NN graph, Algorithm 2
-with R=50, l=40, C=500), searched in the launch configurations the benchmark
-times (the default persistent launch and the autotuned one).  The oracle's
-Algorithm 1 runs on a sample of the queries over the same graph; properties
-that hold at any size are checked on every query."""
+"""GPU parity at the sizes the benchmark runs: the SIFT-like 1M x 128 workload
+(10,000 queries; graph built on the GPU: exact 100-NN graph, Algorithm 2 with
+R=50, l=40, C=500) in the launch configurations the benchmark times (the
+default persistent launch and the autotuned one); the uneven-batch workload
+(DEEP-like 1M x 96) through a captured HIP graph; the 960-d precision
+workload (200k x 960).  The oracle's Algorithm 1 runs on a sample of the
+queries over the same graph; properties that hold at any size are checked on
+every query."""
 import numpy as np
 import pytest
 
@@ -109,4 +111,99 @@ def test_full_size_fp16_sampled_parity(full):
     rr_ids, _ = oracle.rerank(X, Q[SAMPLE], o_pids, k)
     r = compare(X, Q[SAMPLE], ids[SAMPLE], dist[SAMPLE], rr_ids)
     assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    ix.close()
+
+
+def _build(nsg, X, w, dev):
+    Xd = torch.from_numpy(X).to(dev)
+    knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
+    graph, nav, _ = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
+    del knn
+    torch.cuda.synchronize()
+    return Xd, graph, nav
+
+
+def test_uneven_stream_batch_parity():
+    """The uneven-batch workload as the benchmark serves it (DEEP-like 1M x 96,
+    NSG R=32, per-query k in {1,10,100} and L in [10,500], a batch of 1000
+    replayed from one captured HIP graph of the autotuned persistent launch):
+    two replays equal the eager call, and every query of the batch equals the
+    oracle's Algorithm 1 at its own (k, L)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_00143_amd as nsg
+    dev = torch.device("cuda:0")
+    w = datagen.scaled(datagen.DEEP10M_LIKE, 1_000_000, 100_000)
+    X = datagen.base(w)
+    Q = datagen.queries(w)[:1000]
+    print(f"uneven fixture: {w.name}, base {X.shape}", flush=True)
+    Xd, graph, nav = _build(nsg, X, w, dev)
+    G = _np(graph).view(np.uint32)
+    ix = nsg.load_index(Xd, graph, nav, "f32")
+    kk, LL = datagen.uneven_kL(100_000, w.seed + 5)
+    kk, LL = kk[:1000], LL[:1000]
+    Qd = torch.from_numpy(Q).to(dev)
+    kd, Ld = torch.from_numpy(kk).to(dev), torch.from_numpy(LL).to(dev)
+    best, _ = nsg.autotune(ix, Qd, 10, 255, trials=1)
+    opts = dict(best, persistent=1)
+    eager = nsg.search_batched(ix, Qd, k=kd, L=Ld, L_scalar=500, out_stride=100, opts=opts)
+    g = nsg.SearchGraph(ix, Qd, k=kd, L=Ld, L_scalar=500, out_stride=100, opts=opts)
+    for _ in range(2):
+        g.out_ids.fill_(-1)
+        ids, dist = g.launch()
+        torch.cuda.synchronize()
+        for i in range(0, 1000, 37):
+            kv = int(kk[i])
+            assert torch.equal(ids[i, :kv], eager[0][i, :kv]) and torch.equal(dist[i, :kv], eager[1][i, :kv])
+    ids, dist = _np(ids).view(np.uint32).copy(), _np(dist).copy()
+    for i in range(1000):                   # entries past k[i] are not part of the result
+        ids[i, kk[i]:] = 0xFFFFFFFF
+        dist[i, kk[i]:] = np.inf
+    o_ids, _, _, _ = oracle.search(X, G, nav, Q, 100, 500, k_arr=kk, L_arr=LL, threads=16)
+    r = compare(X, Q, ids, dist, o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    g.close()
+    ix.close()
+
+
+@pytest.fixture(scope="module")
+def gist():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_00143_amd as nsg
+    dev = torch.device("cuda:0")
+    w = datagen.scaled(datagen.GIST1M_LIKE, 200_000)
+    X = datagen.base(w)
+    Q = datagen.queries(w)
+    print(f"precision fixture: {w.name}, base {X.shape}", flush=True)
+    Xd, graph, nav = _build(nsg, X, w, dev)
+    yield dict(nsg=nsg, X=X, Q=Q, Xd=Xd, Qd=torch.from_numpy(Q).to(dev), graph=graph, G=_np(graph).view(np.uint32),
+               nav=nav)
+
+
+@pytest.mark.parametrize("dt", ["f32", "e4m3"])
+def test_precision_workload_sampled_parity(gist, dt):
+    """The 960-d precision workload at the size the benchmark reports (GIST-like
+    200k x 960, NSG R=70, 1000 queries, L=250): the walk equals the oracle's
+    Algorithm 1 over the oracle's decoded rows and the output equals the
+    oracle's FP32 re-rank of that pool, on sampled queries."""
+    nsg, X, Q, G, nav, Qd = gist["nsg"], gist["X"], gist["Q"], gist["G"], gist["nav"], gist["Qd"]
+    ix = nsg.load_index(gist["Xd"], gist["graph"], nav, dt)
+    k, L, nq = 10, 250, Q.shape[0]
+    pids = torch.empty((nq, L), dtype=torch.int32, device=Qd.device)
+    pd = torch.empty((nq, L), dtype=torch.float32, device=Qd.device)
+    walk_ids, walk_d = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L,
+                                          opts=dict(rerank=-1, pool_ids=pids, pool_dist=pd, pool_stride=L))
+    ids, dist = nsg.search(ix, Qd, k, L)
+    ids, dist = _np(ids).view(np.uint32), _np(dist)
+    _properties(ids, dist)
+    s = slice(0, None, 8)
+    Xt = X if dt == "f32" else oracle.quantize(dt, X, oracle.scales(dt, X))[1]
+    o_ids, _, _, _, o_pids, _ = oracle.search(Xt, G, nav, Q[s], k, L, pool_stride=L, threads=16)
+    r = compare(Xt, Q[s], _np(walk_ids).view(np.uint32)[s], _np(walk_d)[s], o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    if dt != "f32":
+        rr_ids, _ = oracle.rerank(X, Q[s], o_pids, k)
+        r = compare(X, Q[s], ids[s], dist[s], rr_ids)
+        assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
     ix.close()
