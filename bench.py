@@ -8,7 +8,8 @@ Pipeline (everything on the GPU through libnsg.so, outside the timed region):
   truth     exact top-100 of the test queries (brute force)
   sweep     plain FP32 and FP16 search over L -> the smallest L with mean
             recall@10 >= each target (0.90, 0.95, 0.99)
-  learned   per target: per-query expansion budgets at FP16 pool sizes
+  learned   per target: per-query expansion budgets decided after 16 or 32
+            expansions, at FP16 pool sizes
             L16 + {0, 4, 8, 12, 16}, 1.125 L16, 1.25 L16 and the register-chunk
             boundary (128, 256, 384) below 1.5 L16 (L16: the plain FP16 one):
             budget traces, labels, MLP training and calibration each; the
@@ -240,44 +241,52 @@ def learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, L_base, nq_tes
         log(f"[{target}] L={L_l}: traces {ntr} queries x {len(tr.grid)} budgets in {time.time() - t:.1f}s; "
             f"mean expansions {tr.hops.float().mean().item():.1f}; converged within the grid: {reached.mean():.3f}; "
             f"label histogram over {tr.grid}: {hist.tolist()}")
-        t = time.time()
-        P, mean, istd = ls.train(tr.features[:n_fit].contiguous(), y[:n_fit], seed=7, epochs=30, log=None)
-        torch.cuda.synchronize()
-        yh = ls.predict(P, mean, istd, tr.features[n_fit:].contiguous()).cpu().numpy()
-        hold_mse = float(np.mean((yh - y[n_fit:]) ** 2))
-        base_mse = float(np.mean((y[n_fit:] - y[:n_fit].mean()) ** 2))
-        hits, hops = tr.hits[n_fit:].cpu().numpy(), tr.hops[n_fit:].cpu().numpy()
-        margin = min(0.003, (1.0 - target) / 10)   # held-out slack above the target
-        cal = ls.calibrate(yh, hits, tr.grid, k, target, margin=margin, hops=hops)
-        const = ls.calibrate(np.full_like(yh, y[:n_fit].mean()), hits, tr.grid, k, target, margin=margin, hops=hops)
-        log(f"[{target}] L={L_l}: MLP trained in {time.time() - t:.1f}s; held-out MSE {hold_mse:.4f} (constant "
-            f"predictor {base_mse:.4f}); calibration (c, recall, mean budget, mean expansions) {cal}; "
-            f"constant budget {const}")
-        if not cal:
-            continue
-        ls.install(ix16, P, mean, istd, cal[0], tr.grid)
-        # launch configuration (lanes per row, visited-filter size, waves per
-        # block, persistent grid) of the learned search, autotuned on a batch
-        # of held-out training queries as large as the test batch
-        hb = hq[:nq_test].contiguous()
-        tune, _ = nsg.autotune(ix16, hb, k, L_l, learned_stop=1)
-        o = dict(tune, learned_stop=1)
-        run = lambda: nsg.search_batched(ix16, hb, k_scalar=k, L_scalar=L_l, opts=o)
-        for _ in range(2):
-            run()
-        torch.cuda.synchronize()
-        t0 = time.time()
-        for _ in range(5):
-            ids, _ = run()
-        torch.cuda.synchronize()
-        ms = (time.time() - t0) / 5 * 1e3
-        hr = nsg.recall_hits(ids.view(len(hb), 1, k).contiguous(), hq_truth[:len(hb)].contiguous(),
-                             k).float().mean().item() / k
-        log(f"[{target}] L={L_l} {tune}: held-out training queries: {ms:.3f} ms per {len(hb)}, recall@10 {hr:.4f}")
-        if best is None or ms < best["ms"]:
-            best = dict(ms=ms, L=L_l, launch=tune, P=P, mean=mean, istd=istd, c=cal[0], grid=list(tr.grid),
-                        heldout_mse=hold_mse, const_mse=base_mse, heldout_calibration=cal,
-                        constant_budget_calibration=const)
+        tune = None
+        for hop in (16, 32):
+            # decision after `hop` expansions (budgets below it are raised to it)
+            t = time.time()
+            feats = tr.features if hop == ls.HOP else ls.features_at(ix16, Tq, L_l, hop, k=k)
+            yh_t = np.maximum(y, np.log2(hop))
+            P, mean, istd = ls.train(feats[:n_fit].contiguous(), yh_t[:n_fit], seed=7, epochs=30, log=None)
+            torch.cuda.synchronize()
+            yh = ls.predict(P, mean, istd, feats[n_fit:].contiguous()).cpu().numpy()
+            hold_mse = float(np.mean((yh - yh_t[n_fit:]) ** 2))
+            base_mse = float(np.mean((yh_t[n_fit:] - yh_t[:n_fit].mean()) ** 2))
+            hits, hops = tr.hits[n_fit:].cpu().numpy(), tr.hops[n_fit:].cpu().numpy()
+            margin = min(0.003, (1.0 - target) / 10)   # held-out slack above the target
+            cal = ls.calibrate(yh, hits, tr.grid, k, target, margin=margin, hops=hops, hop=hop)
+            const = ls.calibrate(np.full_like(yh, yh_t[:n_fit].mean()), hits, tr.grid, k, target, margin=margin,
+                                 hops=hops, hop=hop)
+            log(f"[{target}] L={L_l} hop {hop}: MLP trained in {time.time() - t:.1f}s; held-out MSE {hold_mse:.4f} "
+                f"(constant predictor {base_mse:.4f}); calibration (c, recall, mean budget, mean expansions) {cal}; "
+                f"constant budget {const}")
+            if not cal:
+                continue
+            ls.install(ix16, P, mean, istd, cal[0], tr.grid, hop=hop)
+            # launch configuration (lanes per row, visited-filter size, waves per
+            # block, persistent grid) of the learned search, autotuned on a batch
+            # of held-out training queries as large as the test batch
+            hb = hq[:nq_test].contiguous()
+            if tune is None:   # once per pool size
+                tune, _ = nsg.autotune(ix16, hb, k, L_l, learned_stop=1)
+            o = dict(tune, learned_stop=1)
+            run = lambda: nsg.search_batched(ix16, hb, k_scalar=k, L_scalar=L_l, opts=o)
+            for _ in range(2):
+                run()
+            torch.cuda.synchronize()
+            t0 = time.time()
+            for _ in range(5):
+                ids, _ = run()
+            torch.cuda.synchronize()
+            ms = (time.time() - t0) / 5 * 1e3
+            hr = nsg.recall_hits(ids.view(len(hb), 1, k).contiguous(), hq_truth[:len(hb)].contiguous(),
+                                 k).float().mean().item() / k
+            log(f"[{target}] L={L_l} hop {hop} {tune}: held-out training queries: {ms:.3f} ms per {len(hb)}, "
+                f"recall@10 {hr:.4f}")
+            if best is None or ms < best["ms"]:
+                best = dict(ms=ms, L=L_l, hop=hop, launch=tune, P=P, mean=mean, istd=istd, c=cal[0],
+                            grid=list(tr.grid), heldout_mse=hold_mse, const_mse=base_mse, heldout_calibration=cal,
+                            constant_budget_calibration=const)
     return best
 
 
@@ -287,7 +296,7 @@ def check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, target, best):
     nq = Qd.shape[0]
     c = best["c"]
     for _ in range(12):
-        ls.install(ix16, best["P"], best["mean"], best["istd"], c, best["grid"])
+        ls.install(ix16, best["P"], best["mean"], best["istd"], c, best["grid"], hop=best["hop"])
         Bu = torch.empty(nq, dtype=torch.int32, device=dev)
         hq_h = torch.empty(nq, dtype=torch.int64, device=dev)
         ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=best["L"],
@@ -369,7 +378,7 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
                              launch=tune)
         m = learned.get(T)
         if m:
-            ls.install(ix16, m["P"], m["mean"], m["istd"], m["c"], m["grid"])
+            ls.install(ix16, m["P"], m["mean"], m["istd"], m["c"], m["grid"], hop=int(m["hop"]))
             o = dict(m["launch"], learned_stop=1)
             ms, _ = timed(lambda: nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=int(m["L"]), out_ids=out[0],
                                                      out_dist=out[1], opts=o), args.steps, args.warmup)

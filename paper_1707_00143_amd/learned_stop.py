@@ -7,10 +7,10 @@ budget at each value of a geometric grid (16 .. 1024 expansions in 2^(1/4)
 steps); the label is log2 of the smallest budget whose top-k equals the top-k
 of the unbudgeted plain search (the plain search is the judge: the label is
 where the search has converged to its own answer, finite for every query).
-Features are 15 scalars of the search state after the 16th expansion
-(best distance, pool distance profile, distance to the start node, neighbour
-entries per expansion; STOP_FEATURES in the library), the same in every run,
-so one capture serves every grid point.  The network (15 -> 64 -> 64 -> 1,
+Features are 15 scalars of the search state after the decision expansion
+(16 by default; best distance, pool distance profile, distance to the start
+node, neighbour entries per expansion; STOP_FEATURES in the library), the
+same in every run, so one capture serves every grid point.  The network (15 -> 64 -> 64 -> 1,
 ReLU) is trained with the library's forward/backward and Adam kernels on
 z-scored features; the calibration constant c is the smallest one whose
 held-out mean recall meets the target when each query's budget is the grid
@@ -41,8 +41,9 @@ class Traces:
     same: torch.Tensor = None   # [nq][G] int32: |top-k within budget grid[j] ∩ unbudgeted top-k|
 
 
-def traces(index, queries, truth, L, k=10, grid=GRID, chunk=50_000):
-    """Plain search at pool size L under every grid budget; features at HOP."""
+def traces(index, queries, truth, L, k=10, grid=GRID, hop=HOP, chunk=50_000):
+    """Plain search at pool size L under every grid budget; features after
+    expansion `hop` (captured in the run of the first budget >= hop)."""
     nq, d = queries.shape
     dev = queries.device
     feats = torch.empty((nq, STOP_FEATURES), dtype=torch.float32, device=dev)
@@ -50,6 +51,7 @@ def traces(index, queries, truth, L, k=10, grid=GRID, chunk=50_000):
     hops = torch.empty(nq, dtype=torch.int64, device=dev)
     same = torch.empty((nq, len(grid)), dtype=torch.int32, device=dev)
     found = torch.empty((min(chunk, nq), len(grid), k), dtype=torch.int32, device=dev)
+    g_feat = next((g for g, B in enumerate(grid) if B >= hop), len(grid) - 1)
     for s in range(0, nq, chunk):
         e = min(nq, s + chunk)
         q = queries[s:e]
@@ -57,14 +59,25 @@ def traces(index, queries, truth, L, k=10, grid=GRID, chunk=50_000):
             ids = torch.empty((e - s, k), dtype=torch.int32, device=dev)
             dist = torch.empty((e - s, k), dtype=torch.float32, device=dev)
             opts = dict(max_hops=B)
-            if g == 0:
-                opts.update(features=feats[s:e], feature_hop=HOP)
+            if g == g_feat:
+                opts.update(features=feats[s:e], feature_hop=hop)
             search_batched(index, q, k_scalar=k, L_scalar=L, out_ids=ids, out_dist=dist, opts=opts)
             found[:e - s, g].copy_(ids)
         final, _ = search_batched(index, q, k_scalar=k, L_scalar=L, opts=dict(hops=hops[s:e]))
         hits[s:e] = recall_hits(found[:e - s].contiguous(), truth[s:e].contiguous(), k)
         same[s:e] = recall_hits(found[:e - s].contiguous(), final.contiguous(), k)
     return Traces(feats, hits, list(grid), hops, same)
+
+
+def features_at(index, queries, L, hop, k=10, chunk=50_000):
+    """Features after expansion `hop` of the plain search at pool size L."""
+    nq = queries.shape[0]
+    feats = torch.empty((nq, STOP_FEATURES), dtype=torch.float32, device=queries.device)
+    for s in range(0, nq, chunk):
+        e = min(nq, s + chunk)
+        search_batched(index, queries[s:e], k_scalar=k, L_scalar=L,
+                       opts=dict(max_hops=hop, features=feats[s:e], feature_hop=hop))
+    return feats
 
 
 def labels(tr: Traces, k=10):
@@ -149,16 +162,17 @@ def budget(yhat, c, grid, hop=HOP):
     return np.where(np.isfinite(t), B, np.nan)
 
 
-def calibrate(yhat, hits, grid, k=10, target=0.95, margin=0.0, hops=None):
-    """Smallest c (on a 2^(1/16) ladder) whose mean held-out recall >= target.
-    Returns (c, recall, mean budget, mean expansions) (the last needs `hops`,
-    the unbudgeted expansion counts), or None."""
+def calibrate(yhat, hits, grid, k=10, target=0.95, margin=0.0, hops=None, hop=HOP):
+    """Smallest c (on a 2^(1/16) ladder) whose mean held-out recall >= target
+    when the decision is taken after expansion `hop`.  Returns (c, recall,
+    mean budget, mean expansions) (the last needs `hops`, the unbudgeted
+    expansion counts), or None."""
     yhat = np.asarray(yhat)
     h = np.asarray(hits)
     g = np.asarray(grid)
     for j in range(-64, 129):
         c = 2.0 ** (j / 16)
-        B = budget(yhat, c, grid)
+        B = budget(yhat, c, grid, hop)
         col = np.clip(np.searchsorted(g, B), 0, len(g) - 1)
         rec = h[np.arange(len(h)), col] / k
         if rec.mean() >= target + margin:
@@ -172,7 +186,7 @@ def model_blob(P, mean, istd, grid):
     return np.concatenate([p.astype(np.float32).ravel() for p in parts]).tobytes()
 
 
-def install(index, P, mean, istd, c, grid=GRID):
+def install(index, P, mean, istd, c, grid=GRID, hop=HOP):
     n_in = mean.numel()
-    load_stop_model(index, model_blob(P, mean, istd, grid), n_in, HIDDEN, HOP, len(grid))
+    load_stop_model(index, model_blob(P, mean, istd, grid), n_in, HIDDEN, hop, len(grid))
     set_stop_mode(index, True, c)
