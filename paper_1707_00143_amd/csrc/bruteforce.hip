@@ -6,8 +6,11 @@
 // v_mfma_f32_16x16x4f32 (each of the 4 waves: 16 queries x 64 rows), turned
 // into approximate squared distances |q-mu|^2 + |x-mu|^2 - 2 (q-mu).(x-mu),
 // and every value below the query's current threshold is appended to that
-// query's LDS buffer.  A buffer that could overflow on the next tile is
-// sorted and cut back to its Kp best, which tightens the threshold (the
+// query's candidate buffer (device memory: appends are rare once the
+// threshold is tight, and LDS then holds only the staged base chunk, the
+// thresholds and a sort scratch per wave, so several blocks share a CU).  A
+// buffer that could overflow on the next tile is sorted (in the wave's LDS
+// scratch) and cut back to its Kp best, which tightens the threshold (the
 // buffer holds Kp + 2 tiles, so sorts are rare once the threshold is tight).
 // With d <= 128 each wave keeps its 16 centred queries as matrix-core
 // operands in registers for the whole scan and only base rows are staged.
@@ -37,6 +40,7 @@ struct BFParams {
     int nsplit;
     int exclude_self;
     uint32_t *cand_ids;    // [nq][nsplit][Kp]
+    uint64_t *cand_buf;    // [qtiles][nsplit][BQ][cap] candidate buffers
 };
 
 __device__ inline void bsync() { __syncthreads(); }
@@ -105,16 +109,18 @@ __device__ inline void wave_sort_buf(uint64_t *buf, int cnt, int cap, int lane) 
 template <bool AREG>
 __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    float *Qs = reinterpret_cast<float *>(smem);             // [KB][KPAD]
-    float *Xs = Qs + KB * KPAD;                               // [KB][KPAD]
-    float *thr = Xs + KB * KPAD;                              // [BQ]
-    int *cnt = reinterpret_cast<int *>(thr + BQ);             // [BQ]
-    uint64_t *buf = reinterpret_cast<uint64_t *>(cnt + BQ);   // [BQ][cap]
+    float *Xs = reinterpret_cast<float *>(smem);               // [KB][KPAD]
+    float *Qs = Xs + KB * KPAD;                                 // [KB][KPAD] (d > 128 only)
+    float *thr = Qs + (AREG ? 0 : KB * KPAD);                   // [BQ]
+    int *cnt = reinterpret_cast<int *>(thr + BQ);               // [BQ]
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(cnt + BQ); // [4][cap]: one sort buffer per wave
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t q0 = (int64_t)blockIdx.x * BQ;
     const int split = blockIdx.y;
     const int64_t xb = (int64_t)split * p.split_len;
     const int64_t xe = std::min<int64_t>(p.n, xb + p.split_len);
+    uint64_t *buf = p.cand_buf + ((int64_t)blockIdx.x * p.nsplit + split) * (int64_t)BQ * p.cap;
+    uint64_t *sw = scratch + (size_t)w * p.cap;
     if (tid < BQ) { thr[tid] = INFINITY; cnt[tid] = 0; }
     bsync();
     const int rq = lane & 15, kq = lane >> 4;   // MFMA operand row / k group of this lane
@@ -218,10 +224,13 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
         for (int r = w; r < BQ; r += 4) {
             int c = cnt[r];
             if (c > p.cap - BX) {
-                wave_sort_buf(buf + (size_t)r * p.cap, c, p.cap, lane);
+                uint64_t *br = buf + (size_t)r * p.cap;
+                for (int j = lane; j < c; j += 64) sw[j] = br[j];
+                wave_sort_buf(sw, c, p.cap, lane);
+                for (int j = lane; j < p.Kp; j += 64) br[j] = sw[j];
                 if (lane == 0) {
                     cnt[r] = p.Kp;
-                    thr[r] = __uint_as_float((uint32_t)(buf[(size_t)r * p.cap + p.Kp - 1] >> 32));
+                    thr[r] = __uint_as_float((uint32_t)(sw[p.Kp - 1] >> 32));
                 }
             }
         }
@@ -232,10 +241,12 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
         int64_t qi = q0 + r;
         if (qi >= p.nq) continue;
         int c = cnt[r];
-        wave_sort_buf(buf + (size_t)r * p.cap, c, p.cap, lane);
+        const uint64_t *br = buf + (size_t)r * p.cap;
+        for (int j = lane; j < c; j += 64) sw[j] = br[j];
+        wave_sort_buf(sw, c, p.cap, lane);
         uint32_t *dst = p.cand_ids + (qi * p.nsplit + split) * (int64_t)p.Kp;
         for (int j = lane; j < p.Kp; j += 64)
-            dst[j] = j < c ? (uint32_t)(buf[(size_t)r * p.cap + j] & 0xFFFFFFFFu) : NSG_SENT;
+            dst[j] = j < c ? (uint32_t)(sw[j] & 0xFFFFFFFFu) : NSG_SENT;
     }
 }
 
@@ -304,7 +315,6 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     const int Kp = (k + 24 + 31) / 32 * 32;
     int cap = 1;
     while (cap < Kp + 2 * BX) cap <<= 1;
-    if ((size_t)2 * KB * KPAD * 4 + BQ * 8 + (size_t)BQ * cap * 8 > 160 * 1024) cap >>= 1;   // large k: one tile of slack
     // splits: enough blocks to fill the machine, at least a few tiles each
     int64_t qtiles = (nq + BQ - 1) / BQ;
     int64_t want = std::max<int64_t>(1, 2048 / std::max<int64_t>(qtiles, 1));
@@ -320,12 +330,14 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     float *mu = nullptr, *xnorm = nullptr, *qnorm = nullptr;
     double *acc = nullptr;
     uint32_t *cand = nullptr;
+    uint64_t *cbuf = nullptr;
     NSG_HIP(hipMallocAsync((void **)&acc, sizeof(double) * d, st));
     NSG_HIP(hipMemsetAsync(acc, 0, sizeof(double) * d, st));
     NSG_HIP(hipMallocAsync((void **)&mu, sizeof(float) * d, st));
     NSG_HIP(hipMallocAsync((void **)&xnorm, sizeof(float) * n, st));
     NSG_HIP(hipMallocAsync((void **)&qnorm, sizeof(float) * nq, st));
     NSG_HIP(hipMallocAsync((void **)&cand, sizeof(uint32_t) * nq * ncand, st));
+    NSG_HIP(hipMallocAsync((void **)&cbuf, sizeof(uint64_t) * qtiles * nsplit * BQ * cap, st));
     if (int rc = launch_mean(base, n, d, mu, acc, st)) return rc;
     hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, d, mu, xnorm);
     hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, queries, nq, d, mu, qnorm);
@@ -344,8 +356,8 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     p.nsplit = nsplit;
     p.exclude_self = exclude_self ? 1 : 0;
     p.cand_ids = cand;
-    size_t lds = (size_t)2 * KB * KPAD * 4 + BQ * 8 + (size_t)BQ * cap * 8;
-    if (lds > 160 * 1024) return fail(NSG_EUNSUPPORTED, "k=%d needs %zu bytes of LDS", k, lds);
+    p.cand_buf = cbuf;
+    const size_t lds = (size_t)(d <= 128 ? 1 : 2) * KB * KPAD * 4 + BQ * 8 + (size_t)4 * cap * 8;
     if (d <= 128) {
         NSG_HIP(hipFuncSetAttribute((const void *)bf_tile_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds));
@@ -364,6 +376,7 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     hipFreeAsync(xnorm, st);
     hipFreeAsync(qnorm, st);
     hipFreeAsync(cand, st);
+    hipFreeAsync(cbuf, st);
     if (e != hipSuccess) return fail(NSG_EDEVICE, "brute-force launch failed: %s", hipGetErrorString(e));
     return NSG_OK;
 }
