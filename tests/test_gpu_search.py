@@ -213,3 +213,35 @@ def test_repeated_ids_and_tiny_filter_regression(tiny_gpu, nsg):
     r = compare(t["X"], t["Q"], _np(ids).view(np.uint32), _np(dist), o_ids)
     assert r["ok"], r
     ix.close()
+
+
+@pytest.mark.parametrize("L", [200, 330, 500])
+def test_large_pools_launch_invariant(tiny_gpu, nsg, L):
+    """Pools held in 4, 6 and 8 register chunks: for each lanes-per-row layout,
+    every visited-filter size, block shape and grid (one wave per query or the
+    persistent work counter), and the counter and feature-capture variants of
+    the kernel, return bit-identical ids and distances; each layout's result
+    equals the oracle's Algorithm 1 (layouts differ only in FP32 summation
+    order)."""
+    t = tiny_gpu
+    k = 50
+    dev = t["Qd"].device
+    nq = len(t["Q"])
+    o_ids, o_dist, _, _ = oracle.search(t["X"], t["graph"], t["nav"], t["Q"], k, L)
+    for lpr in (8, 16, 32):
+        ref = None
+        runs = [dict(hash_slots=h, waves_per_block=w, persistent=p)
+                for h in (1024, 2048) for w in (1, 4) for p in (0, 1)]
+        runs += [dict(hops=torch.zeros(nq, dtype=torch.int64, device=dev)),
+                 dict(features=torch.empty((nq, nsg.STOP_FEATURES), dtype=torch.float32, device=dev),
+                      feature_hop=16)]
+        for o in runs:
+            ids, dist = nsg.search_batched(t["ix"], t["Qd"], k_scalar=k, L_scalar=L,
+                                           opts=dict(o, lanes_per_row=lpr))
+            if ref is None:
+                ref = (ids.clone(), dist.clone())
+                r = compare(t["X"], t["Q"], _np(ids).view(np.uint32), _np(dist), o_ids, o_dist)
+                assert r["ok"], (L, lpr, {a: b for a, b in r.items() if a != "bad"})
+            else:
+                same = torch.equal(ids, ref[0]) and torch.equal(dist, ref[1])
+                assert same, (L, lpr, {a: b for a, b in o.items() if not isinstance(b, torch.Tensor)})
