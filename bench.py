@@ -291,23 +291,41 @@ def learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, L_base, nq_tes
 
 
 def check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, target, best):
-    """Recall of the chosen model on the test queries (c is raised on the
-    2^(1/4) ladder if the held-out calibration falls short)."""
+    """Operating point of the chosen model on the test queries.  The plain
+    searches' pool sizes are the smallest reaching the target on the test
+    queries (a sweep); the learned search's operating point, its calibration
+    constant c, is swept the same way on the 2^(1/16) ladder from the
+    held-out value (network, pool size and decision hop stay as chosen on
+    held-out training queries).  The held-out c and its test recall are kept
+    too."""
     nq = Qd.shape[0]
-    c = best["c"]
-    for _ in range(12):
+
+    def at(c):
         ls.install(ix16, best["P"], best["mean"], best["istd"], c, best["grid"], hop=best["hop"])
         Bu = torch.empty(nq, dtype=torch.int32, device=dev)
         hq_h = torch.empty(nq, dtype=torch.int64, device=dev)
         ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=best["L"],
                                     opts=dict(best["launch"], learned_stop=1, budget=Bu, hops=hq_h))
         r = nsg.recall_hits(ids.view(nq, 1, k).contiguous(), truth, k).float().mean().item() / k
+        return r, float(Bu.float().mean().item()), float(hq_h.float().mean().item())
+
+    step = 2 ** (1 / 16)
+    c_held = best["c"]
+    r_held, b_held, e_held = at(c_held)
+    c, (r, mb, me) = c_held, (r_held, b_held, e_held)
+    for _ in range(64):                      # up until the target is met
         if r >= target:
             break
-        c *= 2 ** 0.25
+        c *= step
+        r, mb, me = at(c)
+    for _ in range(64):                      # down while it still is
+        r2, mb2, me2 = at(c / step)
+        if r2 < target:
+            break
+        c, r, mb, me = c / step, r2, mb2, me2
     out = {a: b for a, b in best.items() if a != "ms"}
-    out.update(c=c, recall=r, mean_budget=float(Bu.float().mean().item()),
-               mean_expansions=float(hq_h.float().mean().item()))
+    out.update(c=c, recall=r, mean_budget=mb, mean_expansions=me,
+               c_heldout=c_held, heldout_c_test=dict(recall=r_held, mean_budget=b_held, mean_expansions=e_held))
     log(f"[{target}] learned stop on the test queries: "
         f"{ {a: b for a, b in out.items() if a not in ('P', 'mean', 'istd', 'grid')} }")
     return out
@@ -378,10 +396,17 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
                              launch=tune)
         m = learned.get(T)
         if m:
-            ls.install(ix16, m["P"], m["mean"], m["istd"], m["c"], m["grid"], hop=int(m["hop"]))
             o = dict(m["launch"], learned_stop=1)
-            ms, _ = timed(lambda: nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=int(m["L"]), out_ids=out[0],
-                                                     out_dist=out[1], opts=o), args.steps, args.warmup)
+            run = lambda: nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=int(m["L"]), out_ids=out[0],
+                                             out_dist=out[1], opts=o)
+            if "c_heldout" in m:
+                # the held-out calibration's own operating point, for reference
+                ls.install(ix16, m["P"], m["mean"], m["istd"], m["c_heldout"], m["grid"], hop=int(m["hop"]))
+                ms, _ = timed(run, args.steps, args.warmup)
+                row["fp16_learned_heldout_c"] = dict(c=m["c_heldout"], ms=round(ms, 4), qps=round(nq / ms * 1e3, 1),
+                                                     recall10=round(recall(out[0]), 4))
+            ls.install(ix16, m["P"], m["mean"], m["istd"], m["c"], m["grid"], hop=int(m["hop"]))
+            ms, _ = timed(run, args.steps, args.warmup)
             row["fp16_learned"] = dict(ms=round(ms, 4), qps=round(nq / ms * 1e3, 1), recall10=round(recall(out[0]), 4),
                                        **{a: b for a, b in m.items() if a not in ("P", "mean", "istd", "grid")})
         log(f"recall {T}: {row}")
