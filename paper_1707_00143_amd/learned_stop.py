@@ -5,7 +5,7 @@ has no early stop).  The search keeps its pool size L and gets a per-query
 expansion budget.  For every training query the plain search is run with a
 budget at each value of a geometric grid (16 .. 1024 expansions in 2^(1/4)
 steps); the label is log2 of the smallest budget whose top-k equals the top-k
-of the unbudgeted plain search (the plain search is the judge: the label is
+of the unbudgeted plain search (the plain search is the reference: the label is
 where the search has converged to its own answer, finite for every query).
 Features are 15 scalars of the search state after the decision expansion
 (16 by default; best distance, pool distance profile, distance to the start
