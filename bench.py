@@ -52,11 +52,12 @@ def source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the plain FP32 search from the committed
-    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known
-    size), or None if the library sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "search_f32_sift1m_like_traffic.json")
+def measured_traffic(kernel):
+    """HBM bytes per launch of a timed search ("f32": plain FP32; "f16_learned":
+    FP16 + learned stop) from the committed rocprofv3 PMC summary (FETCH_SIZE
+    and WRITE_SIZE scaled by a copy of known size), or None if the library
+    sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"search_{kernel}_sift1m_like_traffic.json")
     try:
         with open(path) as fh:
             t = json.load(fh)
@@ -419,29 +420,62 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
     qps32, ms32, r32 = head["plain_fp32"]["qps"], head["plain_fp32"]["ms"], head["plain_fp32"]["recall10"]
     log(f"plain FP32 L={L32}: {ms32:.3f} ms/step, {qps32:,.0f} QPS, recall@10 {r32:.4f}")
     log(f"FP16 + learned stop: {ms16:.3f} ms/step, {qps16:,.0f} QPS, recall@10 {r16:.4f}")
-    # the plain FP32 step again, for the roofline
+    m = learned[args.target]
+    L16 = int(m["L"])
+    d = X.shape[1]
+    # per-query budgets of the timed configuration (same kernel: the budget
+    # output is one of the learned-stop kernel's options)
+    ls.install(ix16, m["P"], m["mean"], m["istd"], m["c"], m["grid"], hop=int(m["hop"]))
+    Bu = torch.zeros(nq, dtype=torch.int32, device=dev)
+    nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=L16, out_ids=out[0], out_dist=out[1],
+                       opts=dict(m["launch"], learned_stop=1, budget=Bu))
+    Bu = Bu.cpu().numpy()
+    # the plain FP32 step again (its own roofline, secondary)
     ms32, _ = timed(lambda: nsg.search_batched(ix32, Qd, k_scalar=k, L_scalar=L32, out_ids=out[0], out_dist=out[1],
                                                opts=launch32), args.steps, args.warmup)
-    out32 = out
+    out32 = out[0].cpu().numpy().view(np.uint32).copy()
 
-    # ---------------- roofline of the dominant kernel (plain FP32 search) ----------------
-    # counts with a visited filter large enough never to forget (= the
-    # oracle's exact visited set), so only the method's own bytes are credited
-    nsg.search_batched(ix32, Qd, k_scalar=k, L_scalar=L32,
-                       opts=dict(hops=hops, ndist=ndist, nedges=nedge, hash_slots=16384))
-    lpr32 = int(launch32["lanes_per_row"]) or 8
-    torch.cuda.synchronize()
-    d = X.shape[1]
-    H, N, E = hops.sum().item(), ndist.sum().item(), nedge.sum().item()
-    alg_bytes = N * d * 4 + (E + H) * 4 + nq * (d * 4 + k * 8)
-    achieved = alg_bytes / (ms32 / 1e3) / 1e9
-    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=8000.0, unit="GB/s",
-                frac=round(achieved / 8000.0, 4), traffic=measured_traffic(),
-                kernel=f"search_kernel<F32, lanes per row {lpr32}, chunks per lane {-(-32 // lpr32)}, plain, "
-                       f"2 pool chunks>", launch=launch32,
-                bytes_per_launch=int(alg_bytes),
-                per_query=dict(hops=H / nq, ndist=N / nq, edges=E / nq))
-    log(f"roofline: {roof}")
+    # ---------------- CPU baseline leg (the oracle) ----------------
+    # timed: Algorithm 1 on the host cores (all of them, then one thread);
+    # not timed: the oracle's exact per-query counts (expansions, distance
+    # evaluations, neighbour entries read) of the two timed GPU searches,
+    # which the rooflines below credit as algorithmic bytes
+    cpu, counts = None, None
+    if not args.no_cpu:
+        cpu, counts = cpu_leg(args, X, Q, graph, nav, k, L32, out32, L16, Bu)
+    else:
+        counts = gpu_counts(nsg, torch, dev, ix32, ix16, Qd, k, L32, L16, Bu)
+
+    # ---------------- rooflines ----------------
+    # algorithmic bytes per query: rows gathered (N_dist x row bytes), the
+    # neighbour rows read (entries + 1 per expansion, 4 B each), the query and
+    # the output; the FP16 search also re-reads its final pool in FP32 for the
+    # re-rank (pool entries x d x 4)
+    def alg_bytes(c, row_bytes, rerank_rows):
+        return (c["ndist"] * row_bytes + (c["nedges"] + c["hops"]) * 4 + nq * (d * 4 + k * 8)
+                + rerank_rows * d * 4)
+
+    rb16 = -(-d // 8) * 16
+    b16 = alg_bytes(counts["f16_learned"], rb16, counts["f16_learned"]["pool"])
+    b32 = alg_bytes(counts["f32"], -(-d // 4) * 16, 0)
+    ach16 = b16 / (ms16 / 1e3) / 1e9
+    ach32 = b32 / (ms32 / 1e3) / 1e9
+    lpr = int(m["launch"].get("lanes_per_row") or 8)
+    roof = dict(bound="hbm", achieved=round(ach16, 1), peak=8000.0, unit="GB/s", frac=round(ach16 / 8000.0, 4),
+                traffic=measured_traffic("f16_learned"),
+                kernel=f"search_kernel<F16, lanes per row {lpr}, chunks per lane {max(1, -(-(rb16 // 16) // lpr))}, "
+                       f"learned stop, {2 if L16 <= 128 else 4 if L16 <= 256 else 6 if L16 <= 384 else 8} pool chunks>",
+                launch=m["launch"], bytes_per_launch=int(b16), ms_per_launch=ms16,
+                per_query={a: round(v / nq, 2) for a, v in counts["f16_learned"].items()},
+                counts=counts["source"])
+    lpr32 = int(launch32.get("lanes_per_row") or 8)
+    roof32 = dict(bound="hbm", achieved=round(ach32, 1), peak=8000.0, unit="GB/s", frac=round(ach32 / 8000.0, 4),
+                  traffic=measured_traffic("f32"),
+                  kernel=f"search_kernel<F32, lanes per row {lpr32}, chunks per lane {-(-(d // 4) // lpr32)}, plain, "
+                         f"2 pool chunks>", launch=launch32, bytes_per_launch=int(b32), ms_per_launch=round(ms32, 4),
+                  per_query={a: round(v / nq, 2) for a, v in counts["f32"].items()}, counts=counts["source"])
+    log(f"roofline FP16 + learned stop: {roof}")
+    log(f"roofline plain FP32: {roof32}")
 
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
@@ -451,27 +485,7 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
         torch.cuda.synchronize()
         log("calibration copy: 2 x 1 GiB read + 1 GiB written")
 
-    # ---------------- CPU baseline: the oracle on a bounded sample ----------------
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        g_np = graph.cpu().numpy().view(np.uint32)
-        threads = len(os.sched_getaffinity(0))
-        m = 256
-        t = time.time()
-        oracle.search(X, g_np, nav, Q[:m], k, L32, threads=threads)
-        el = time.time() - t
-        m2 = int(min(nq, max(m, m * args.cpu_seconds / max(el, 1e-3))))
-        t = time.time()
-        o_ids, _, _, _ = oracle.search(X, g_np, nav, Q[:m2], k, L32, threads=threads)
-        el = time.time() - t
-        same = float(np.mean([set(a) == set(b) for a, b in zip(o_ids, out32[0][:m2].cpu().numpy().view(np.uint32))]))
-        cpu = dict(value=round(m2 / el, 1), unit="queries/s", cores=threads, kind="oracle",
-                   sample=f"first {m2} of {nq} test queries, plain Algorithm 1 at L={L32}, k={k}, "
-                          f"same graph; {el:.1f}s; GPU id sets equal on {same * 100:.1f}%")
-        log(f"cpu baseline: {cpu}")
-
-    d = X.shape[1]
+    f16row = head.get("plain_fp16")
     res = {
         "metric": "QPS at recall@10>=0.95, 1M x 128: FP16 storage + learned early stop (vs plain FP32)",
         "value": qps16,
@@ -483,24 +497,117 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16 storage, f32 accumulate, f32 re-rank",
         "data": "synthetic",
         "config": {
             "workload": f"{w.name}: {X.shape[0]} x {d} float32 latent Gaussian mixture, {nq} queries, "
                         f"NSG R={w.R} l={w.Lb} C={w.C} from exact {w.K}-NN graph; k={k}",
             "plain_fp32": head["plain_fp32"],
             "fp16_learned": head["fp16_learned"],
-            "plain_fp16": head.get("plain_fp16"),
+            "plain_fp16": f16row,
+            "fp16_learned_heldout_c": head.get("fp16_learned_heldout_c"),
             "speedup_vs_plain_fp32": round(qps16 / qps32, 3),
+            "speedup_vs_plain_fp16": round(qps16 / f16row["qps"], 3) if f16row else None,
+            "speedup_heldout_c_vs_plain_fp32": round(head["fp16_learned_heldout_c"]["qps"] / qps32, 3)
+            if head.get("fp16_learned_heldout_c") else None,
             "by_recall_target": {str(T): v for T, v in per_target.items()},
             "index": dict(nav=nav, repair_edges=rep, aod=round(deg.mean().item(), 2), mod=int(deg.max().item()),
                           knn_s=round(t_knn, 2), build_s=round(t_build, 2)),
             "sweep_fp32": sweep,
+            "roofline_plain_fp32": roof32,
         },
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))
+
+
+def cpu_leg(args, X, Q, graph, nav, k, L32, out32, L16, Bu):
+    """The oracle (plain C Algorithm 1) timed on the host: all cores on a
+    bounded sample, then one thread on 1,000 queries (the paper's
+    single-thread protocol, Sec. 4.1.2); and, untimed, its exact counts for
+    the two timed GPU searches (plain FP32 at L32; FP16 decoded rows at L16
+    with the learned stop's per-query budgets)."""
+    import oracle
+    g_np = graph.cpu().numpy().view(np.uint32)
+    nq = Q.shape[0]
+    threads = len(os.sched_getaffinity(0))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    m = 256
+    t = time.time()
+    oracle.search(X, g_np, nav, Q[:m], k, L32, threads=threads)
+    el = time.time() - t
+    m2 = int(min(nq, max(m, m * args.cpu_seconds / max(el, 1e-3))))
+    hops = np.zeros(m2, np.int64)
+    ne = np.zeros(m2, np.int64)
+    t = time.time()
+    o_ids, _, o_h, o_nd = oracle.search(X, g_np, nav, Q[:m2], k, L32, threads=threads, nedges=ne)
+    el = time.time() - t
+    same = float(np.mean([set(a) == set(b) for a, b in zip(o_ids, out32[:m2])]))
+    m1 = min(nq, 1000)
+    t = time.time()
+    oracle.search(X, g_np, nav, Q[:m1], k, L32, threads=1)
+    el1 = time.time() - t
+    cpu = dict(value=round(m2 / el, 1), unit="queries/s", cores=threads, kind="oracle",
+               sample=f"first {m2} of {nq} test queries, plain Algorithm 1 at L={L32}, k={k}, same graph; "
+                      f"{el:.1f}s; GPU id sets equal on {same * 100:.1f}%",
+               single_thread=dict(value=round(m1 / el1, 1), unit="queries/s", cores=1,
+                                  sample=f"first {m1} test queries, {el1:.1f}s"),
+               cpu_model=model)
+    log(f"cpu baseline: {cpu}")
+    counts = dict(source="oracle (exact visited set)")
+    if m2 < nq:
+        ne = np.zeros(nq, np.int64)
+        _, _, o_h, o_nd = oracle.search(X, g_np, nav, Q, k, L32, threads=threads, nedges=ne)
+    counts["f32"] = dict(hops=int(o_h.sum()), ndist=int(o_nd.sum()), nedges=int(ne.sum()))
+    _, Xt = oracle.quantize("f16", X, oracle.scales("f16", X))
+    ne16 = np.zeros(nq, np.int64)
+    _, _, h16, nd16, pids, _ = oracle.search(Xt, g_np, nav, Q, k, L16, pool_stride=L16, max_hops=Bu,
+                                             threads=threads, nedges=ne16)
+    counts["f16_learned"] = dict(hops=int(h16.sum()), ndist=int(nd16.sum()), nedges=int(ne16.sum()),
+                                 pool=int((pids != 0xFFFFFFFF).sum()))
+    log(f"oracle counts: {counts}")
+    return cpu, counts
+
+
+def gpu_counts(nsg, torch, dev, ix32, ix16, Qd, k, L32, L16, Bu):
+    """Counts of the two timed searches from the GPU's own counters with a
+    visited filter of 16,384 slots (without the oracle, --no-cpu): the
+    filter may forget a few nodes, so distance evaluations can be slightly
+    above the method's."""
+    nq = Qd.shape[0]
+    out = {"source": "GPU counters, 16384-slot visited filter (upper bound)"}
+    for key, ix, L, mh in (("f32", ix32, L32, None), ("f16_learned", ix16, L16, Bu)):
+        h, nd, ne = (torch.zeros(nq, dtype=torch.int64, device=dev) for _ in range(3))
+        if mh is None:
+            nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(hops=h, ndist=nd, nedges=ne,
+                                                                        hash_slots=16384))
+            out[key] = dict(hops=int(h.sum().item()), ndist=int(nd.sum().item()), nedges=int(ne.sum().item()))
+        else:
+            pool = torch.full((nq, L), -1, dtype=torch.int32, device=dev)
+            pd = torch.empty((nq, L), dtype=torch.float32, device=dev)
+            # per-query budgets as expansion caps, one launch per distinct budget
+            tot = dict(hops=0, ndist=0, nedges=0, pool=0)
+            for B in sorted(set(int(b) for b in mh)):
+                sel = torch.from_numpy(np.where(mh == B)[0]).to(dev)
+                q = Qd.index_select(0, sel).contiguous()
+                hh, nn, ee = (torch.zeros(len(sel), dtype=torch.int64, device=dev) for _ in range(3))
+                pp = torch.full((len(sel), L), -1, dtype=torch.int32, device=dev)
+                pdd = torch.empty((len(sel), L), dtype=torch.float32, device=dev)
+                nsg.search_batched(ix, q, k_scalar=k, L_scalar=L, opts=dict(hops=hh, ndist=nn, nedges=ee,
+                                   hash_slots=16384, max_hops=B if B > 0 else 0, pool_ids=pp, pool_dist=pdd,
+                                   pool_stride=L))
+                tot["hops"] += int(hh.sum().item())
+                tot["ndist"] += int(nn.sum().item())
+                tot["nedges"] += int(ee.sum().item())
+                tot["pool"] += int((pp != -1).sum().item())
+            out[key] = tot
+    return out
 
 
 def uneven(args, torch, nsg, datagen, dev):

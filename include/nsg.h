@@ -21,8 +21,9 @@
  *   - Return value: NSG_OK (0) or a negative nsg_status; nsg_last_error()
  *     gives a message for the calling host thread.  No C++ exception crosses
  *     this ABI.
- *   - Limits: n < 2^31, 1 <= d <= 4096, 1 <= R <= 128, 1 <= L <= 512,
- *     1 <= k <= 512.
+ *   - Limits: n < 2^31, 1 <= d <= 1024, 1 <= R <= 128, 1 <= L <= 512,
+ *     1 <= k <= 512 (nsg_knn_bruteforce: 1 <= k <= 160).  Arguments outside
+ *     them return NSG_EINVAL before anything is enqueued.
  */
 #ifndef NSG_H
 #define NSG_H
@@ -100,7 +101,9 @@ int nsg_index_info(const nsg_index *idx, int64_t *n, int32_t *d, int32_t *R,
  * walk uses the decoded rows s_j * code and the final pool is re-ranked with
  * exact FP32 distances before the first k are emitted.
  * Outputs out_ids[nq][k], out_dist[nq][k] (device, caller-allocated).
- * nq = 0 is a no-op.
+ * nq = 0 is a no-op.  Batches of 4096 queries or more run on a persistent
+ * grid whose work counter the library allocates once per stream (the first
+ * such call on a stream allocates it; later calls on that stream reuse it).
  */
 int nsg_search(const nsg_index *idx, const float *queries, int64_t nq,
                int32_t k, int32_t L, uint32_t *out_ids, float *out_dist,
@@ -109,7 +112,7 @@ int nsg_search(const nsg_index *idx, const float *queries, int64_t nq,
 /* Options of nsg_search_batched (host struct; zero-initialise, then set). */
 typedef struct nsg_search_opts {
     int32_t persistent;      /* 1: persistent grid with an atomic work counter */
-    int32_t waves_per_block; /* 0: autotuned / default */
+    int32_t waves_per_block; /* 0: default; else 1..4 (the kernels are built for <= 256 threads) */
     int32_t hash_slots;      /* visited-filter slots per query (power of 2); 0: default */
     int32_t blocks;          /* persistent grid size; 0: one wave per resident slot */
     int32_t learned_stop;    /* 1: use the loaded early-stop model (queries with L >= 16) */
@@ -127,8 +130,12 @@ typedef struct nsg_search_opts {
     int64_t *nedges;         /* device [nq] valid neighbour entries read over all expansions, or NULL */
     int32_t lanes_per_row;   /* lanes that gather one row (8, 16, 32, 64); 0: default */
     uint32_t *counter;       /* device scratch word for the persistent work counter (reset by the
-                                call); NULL: allocated per call (not usable under graph capture) */
+                                call); NULL: the library's counter for the calling stream, allocated
+                                on the first persistent search on that stream and kept */
     int32_t max_hops;        /* > 0: every query stops after this many expansions; 0: no budget */
+    int32_t *clamped;        /* device int32 counter (caller-initialised), or NULL: incremented
+                                once for every query whose k[i] lies outside [0, out_stride] or
+                                whose L[i] lies outside [1, L_scalar] (see below) */
 } nsg_search_opts;
 
 /*
@@ -137,6 +144,12 @@ typedef struct nsg_search_opts {
  * out_stride >= max k; entries past k[i] are left untouched.  `opts` may be
  * NULL.  Same algorithm and result definition as nsg_search: every query's
  * output equals its own nsg_search at (k[i], L[i]).
+ * The per-query arrays live on the device, so they are not checked on the
+ * host: a k[i] outside [0, out_stride] is clamped into it (k[i] = 0 writes
+ * nothing) and an L[i] outside [1, L_scalar] is clamped into that range; each
+ * such query is counted in opts->clamped when it is given.  The persistent
+ * grid (opts->persistent) with opts->counter NULL uses a work counter the
+ * library allocates once per stream (the first call on a stream allocates).
  */
 int nsg_search_batched(const nsg_index *idx, const float *queries, int64_t nq,
                        const int32_t *k, const int32_t *L,
@@ -154,7 +167,10 @@ typedef struct nsg_search_graph nsg_search_graph;   /* opaque, owned by the libr
  * Capture one nsg_search_batched call (same arguments) into a HIP graph and
  * instantiate it.  The buffers are bound at capture: refill `queries` (and
  * k / L) in place, then nsg_search_graph_launch replays the whole batch with
- * one launch.  With opts->persistent the graph owns its work counter.
+ * one launch.  With opts->persistent the graph owns its work counter.  A
+ * graph captured with opts->learned_stop holds the index's early-stop model
+ * and calibration as they were at capture: while such a graph exists,
+ * nsg_load_stop_model and nsg_set_stop_mode on that index return NSG_ESTATE.
  */
 int nsg_search_graph_create(const nsg_index *idx, const float *queries, int64_t nq,
                             const int32_t *k, const int32_t *L, int32_t k_scalar,
@@ -187,7 +203,8 @@ int nsg_autotune(const nsg_index *idx, const float *queries, int64_t nq, int32_t
  * (|q|^2 + |x|^2 - 2 q.x), over-fetched, then re-ranked with exact FP32
  * differences (sum of (q_j - x_j)^2).  exclude_self != 0: queries are the base
  * rows themselves and query i never returns row i (kNN graph).  base[n][d],
- * queries[nq][d] FP32; out_ids / out_dist [nq][k].  k <= 512.
+ * queries[nq][d] FP32; out_ids / out_dist [nq][k].  1 <= k <= 160.  Scratch
+ * memory is allocated and freed on `stream` (stream-ordered allocations).
  */
 int nsg_knn_bruteforce(const float *base, int64_t n, const float *queries,
                        int64_t nq, int32_t d, int32_t k, int32_t exclude_self,
@@ -242,7 +259,9 @@ int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t *knn,
 int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes,
                         int32_t in, int32_t h, int32_t hop, int32_t grid_n);
 
-/* Enable (1) or disable (0) the early stop and set its calibration c > 0. */
+/* Enable (1) or disable (0) the early stop and set its calibration c > 0.
+ * Both this call and nsg_load_stop_model return NSG_ESTATE while a search
+ * graph captured with the early stop exists on the index (see above). */
 int nsg_set_stop_mode(nsg_index *idx, int32_t enabled, float calib_c);
 
 /*

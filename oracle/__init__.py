@@ -23,6 +23,12 @@ Parity status per function (see the tests named):
                   (test_oracle_mlp)
   stop_features   pinned: hand-worked state with literal expected values
                   (test_oracle_mlp)
+  search_sharded  pinned: one shard = the plain search; exhaustive pools in
+  / merge_topk    every shard = exact kNN of the whole base; hand merge
+                  with ties and padding (test_oracle_shards)
+  rerank          pinned: hand case with a tie and padding; a pool holding
+                  the exact top-k returns it (integer data, exact distances);
+                  per-query stride (test_oracle_rerank)
 """
 from __future__ import annotations
 
@@ -63,7 +69,7 @@ def _get():
             "oracle_l2sq_f64": (f64, [P, P, i32]),
             "oracle_knn": (i32, [P, i64, i32, P, i64, i32, i32, i32, P, P]),
             "oracle_search_batch": (i32, [P, i64, i32, P, i32, u32, P, i64, i32, i32, P, P,
-                                          i32, P, P, P, P, P, P, i32, P, i32]),
+                                          i32, P, P, P, P, P, P, i32, P, P, i32]),
             "oracle_search_one": (i32, [P, i64, i32, P, i32, u32, P, i32, i64, P, P, P,
                                         P, i64, P, P, i64, P]),
             "oracle_centroid": (i32, [P, i64, i32, P]),
@@ -139,10 +145,12 @@ def knn_graph(base, K):
 # --------------------------------------------------------------------------
 
 def search(base, graph, start, queries, k, L, k_arr=None, L_arr=None, pool_stride=0,
-           max_hops=None, threads=0):
+           max_hops=None, threads=0, nedges=None):
     """Batched Algorithm 1 from `start`.  Returns (ids, dist, hops, ndist[, pool_ids,
     pool_dist]).  With per-query k_arr / L_arr the outputs are [nq][max k].
-    max_hops: optional per-query expansion budget (<= 0: none)."""
+    max_hops: optional per-query expansion budget (<= 0: none).  nedges: an
+    optional int64 [nq] array that receives the neighbour entries each query
+    read (the valid row prefixes of its expanded nodes)."""
     base, graph, queries = _f32(base), _u32(graph), _f32(queries)
     n, d = base.shape
     R = graph.shape[1]
@@ -159,10 +167,14 @@ def search(base, graph, start, queries, k, L, k_arr=None, L_arr=None, pool_strid
         pids = np.empty((nq, pool_stride), np.uint32)
         pd = np.empty((nq, pool_stride), np.float32)
     mh = None if max_hops is None else np.ascontiguousarray(np.broadcast_to(max_hops, (nq,)), np.int32)
+    ne = None
+    if nedges is not None:
+        assert nedges.dtype == np.int64 and nedges.shape == (nq,) and nedges.flags.c_contiguous
+        ne = nedges
     _check(_get().oracle_search_batch(
         _p(base), n, d, _p(graph), R, int(start), _p(queries), nq, int(k), int(L),
         _p(k_arr_c), _p(L_arr_c), kst, _p(ids), _p(dist), _p(hops), _p(nd),
-        _p(pids), _p(pd), int(pool_stride), _p(mh), int(threads)), "search")
+        _p(pids), _p(pd), int(pool_stride), _p(mh), _p(ne), int(threads)), "search")
     if pool_stride:
         return ids, dist, hops, nd, pids, pd
     return ids, dist, hops, nd
@@ -190,6 +202,50 @@ def search_one(base, graph, start, q, L, stop_hop=-1, trace_cap=4096, vis_cap=1 
                 pool_checked=pchk[:size].astype(bool), trace=trace[:min(h, trace_cap)].copy(),
                 vis_ids=vid[:min(nv, vis_cap)].copy(), vis_dist=vdist[:min(nv, vis_cap)].copy(),
                 hops=h, ndist=ndist)
+
+
+def merge_topk(ids, dist, k):
+    """Top k of the union of per-shard result lists: ids/dist [nq][S][k_s]
+    (global ids, SENT/+inf padding), ordered by (distance, id); the plain
+    definition of the merge (a sort of the concatenation), padded with
+    (SENT, +inf) when fewer than k results exist."""
+    ids = np.asarray(ids, np.uint32)
+    dist = np.asarray(dist, np.float32)
+    nq = ids.shape[0]
+    out_i = np.full((nq, k), SENT, np.uint32)
+    out_d = np.full((nq, k), np.inf, np.float32)
+    for q in range(nq):
+        ii, dd = ids[q].ravel(), dist[q].ravel()
+        ok = ii != SENT
+        ii, dd = ii[ok], dd[ok]
+        order = np.lexsort((ii, dd))[:k]
+        out_i[q, :len(order)] = ii[order]
+        out_d[q, :len(order)] = dd[order]
+    return out_i, out_d
+
+
+def search_sharded(base, offsets, graph, navs, queries, k, L, threads=0):
+    """The partitioned scheme of the paper's large-scale experiments (one
+    sub-NSG per subset, every query searched in every subset, the per-subset
+    results merged; Sec. 4.2 "Search On DEEP100M", Sec. 4.3): shard s holds
+    base rows offsets[s] .. offsets[s+1] - 1 and its own graph rows (local
+    ids, same rows of `graph`) and navigating node navs[s] (local id).
+    Algorithm 1 runs in each shard at pool size L; its top k (mapped to
+    global ids) are merged by merge_topk.  Returns (ids, dist, per-shard
+    ids [nq][S][k], per-shard dist)."""
+    base, graph, queries = _f32(base), _u32(graph), _f32(queries)
+    S = len(offsets) - 1
+    nq = queries.shape[0]
+    sid = np.full((nq, S, k), SENT, np.uint32)
+    sd = np.full((nq, S, k), np.inf, np.float32)
+    for s in range(S):
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        ids, dist, _, _ = search(base[a:b], graph[a:b], int(navs[s]), queries, k, L, threads=threads)
+        ok = ids != SENT
+        sid[:, s] = np.where(ok, ids + np.uint32(a), SENT)
+        sd[:, s] = dist
+    out_i, out_d = merge_topk(sid, sd, k)
+    return out_i, out_d, sid, sd
 
 
 # --------------------------------------------------------------------------

@@ -219,11 +219,11 @@ static int ws_vis_push(ws_t *w, float dist, uint32_t id)
  */
 static int search_core(const float *base, int d, const uint32_t *graph, int R,
                        uint32_t start, const float *q, int L, ws_t *w,
-                       int64_t *hops_out, int64_t *ndist_out,
+                       int64_t *hops_out, int64_t *ndist_out, int64_t *nedges_out,
                        int keep_visited, int64_t stop_hop,
                        uint32_t *trace, int64_t trace_cap)
 {
-    int64_t hops = 0, ndist = 0;
+    int64_t hops = 0, ndist = 0, nedges = 0;
     w->cur++;
     if (w->cur == 0) {                      /* stamp wrap-around */
         memset(w->stamp, 0, sizeof(uint32_t) * (size_t)w->n);
@@ -255,6 +255,7 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
         for (int j = 0; j < R; ++j) {
             uint32_t u = row[j];
             if (u == SENT) break;
+            nedges++;
             if (w->stamp[u] == w->cur) continue;
             w->stamp[u] = w->cur;
             float du = oracle_l2sq_f32(q, base + (int64_t)u * d, d);
@@ -271,6 +272,7 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
     }
     if (hops_out) *hops_out = hops;
     if (ndist_out) *ndist_out = ndist;
+    if (nedges_out) *nedges_out = nedges;
     return size;
 }
 
@@ -282,6 +284,8 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
  * pool_ids/pool_dist ([nq][pool_stride], optional) receive the final pool.
  * max_hops_arr (optional): per-query expansion budget (the learned early
  * stop); a query stops after that many expansions; values <= 0: no budget.
+ * nedges (optional): per query, the neighbour entries read (valid row
+ * prefixes of the expanded nodes, visited or not).
  * threads <= 0 uses the OpenMP default.
  */
 int oracle_search_batch(const float *base, int64_t n, int d,
@@ -291,7 +295,7 @@ int oracle_search_batch(const float *base, int64_t n, int d,
                         int k_stride, uint32_t *out_ids, float *out_dist,
                         int64_t *hops, int64_t *ndist,
                         uint32_t *pool_ids, float *pool_dist, int pool_stride,
-                        const int32_t *max_hops_arr, int threads)
+                        const int32_t *max_hops_arr, int64_t *nedges, int threads)
 {
     if (n < 1 || d < 1 || R < 1 || start >= (uint64_t)n || nq < 0) return -1;
     int maxL = L;
@@ -308,9 +312,9 @@ int oracle_search_batch(const float *base, int64_t n, int d,
             int kk = k_arr ? k_arr[qi] : k;
             int LL = L_arr ? L_arr[qi] : L;
             int64_t budget = (max_hops_arr && max_hops_arr[qi] > 0) ? max_hops_arr[qi] : -1;
-            int64_t h = 0, nd = 0;
+            int64_t h = 0, nd = 0, ne = 0;
             int size = search_core(base, d, graph, R, start, queries + qi * (int64_t)d,
-                                   LL, &w, &h, &nd, 0, budget, NULL, 0);
+                                   LL, &w, &h, &nd, &ne, 0, budget, NULL, 0);
             for (int j = 0; j < kk; ++j) {
                 out_ids[qi * k_stride + j] = j < size ? w.pool[j].id : SENT;
                 out_dist[qi * k_stride + j] = j < size ? w.pool[j].dist : INFINITY;
@@ -322,6 +326,7 @@ int oracle_search_batch(const float *base, int64_t n, int d,
                 }
             if (hops) hops[qi] = h;
             if (ndist) ndist[qi] = nd;
+            if (nedges) nedges[qi] = ne;
         }
         ws_free(&w);
     }
@@ -346,7 +351,7 @@ int oracle_search_one(const float *base, int64_t n, int d,
     ws_t w;
     if (ws_init(&w, n, L + R) != 0) { ws_free(&w); return -2; }
     int64_t h = 0, nd = 0;
-    int size = search_core(base, d, graph, R, start, q, L, &w, &h, &nd, 1,
+    int size = search_core(base, d, graph, R, start, q, L, &w, &h, &nd, NULL, 1,
                            stop_hop, trace, trace_cap);
     for (int j = 0; j < size; ++j) {
         if (pool_ids) pool_ids[j] = w.pool[j].id;
@@ -393,7 +398,7 @@ int oracle_navigating_node(const float *base, int64_t n, int d,
     oracle_centroid(base, n, d, c);
     ws_t w;
     if (ws_init(&w, n, Lb + K) != 0) { ws_free(&w); free(c); return -2; }
-    search_core(base, d, knn, K, rand_start, c, Lb, &w, NULL, NULL, 0, -1, NULL, 0);
+    search_core(base, d, knn, K, rand_start, c, Lb, &w, NULL, NULL, NULL, 0, -1, NULL, 0);
     *nav = w.pool[0].id;
     ws_free(&w);
     free(c);
@@ -445,7 +450,7 @@ static int collect_select(const float *base, int64_t n, int d,
                           int C, int m, uint32_t v, ws_t *w, uint32_t *row)
 {
     const float *qv = base + (int64_t)v * d;
-    search_core(base, d, knn, K, nav, qv, Lb, w, NULL, NULL, 1, -1, NULL, 0);
+    search_core(base, d, knn, K, nav, qv, Lb, w, NULL, NULL, NULL, 1, -1, NULL, 0);
     /* the visited stamp marks exactly the visited ids; add unvisited kNN ids */
     for (int j = 0; j < K; ++j) {
         uint32_t u = knn[(int64_t)v * K + j];
@@ -532,7 +537,7 @@ int oracle_repair(const float *base, int64_t n, int d, uint32_t *graph, int m,
         if (scan >= n) break;
         uint32_t u = (uint32_t)scan;
         const float *qu = base + (int64_t)u * d;
-        int size = search_core(base, d, graph, m, nav, qu, Lb, &w, NULL, NULL, 0,
+        int size = search_core(base, d, graph, m, nav, qu, Lb, &w, NULL, NULL, NULL, 0,
                                -1, NULL, 0);
         int64_t wsel = -1;
         for (int t = 0; t < size; ++t) {

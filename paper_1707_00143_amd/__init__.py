@@ -55,6 +55,7 @@ class SearchOpts(ctypes.Structure):
         ("lanes_per_row", ctypes.c_int32),
         ("counter", ctypes.c_void_p),
         ("max_hops", ctypes.c_int32),
+        ("clamped", ctypes.c_void_p),
     ]
 
 

@@ -189,11 +189,14 @@ extern "C" int nsg_load_index(const float *base, int64_t n, int32_t d, const uin
     hipGetDevice(&ix->device);
     const int ld32 = ix->row_chunks_f32 * 4;
     auto cleanup = [&](int rc) { nsg_free_index(ix); return rc; };
-    if (hipMalloc(&ix->base_f32, sizeof(float) * n * ld32) != hipSuccess ||
+    // row tables carry kRowTailBytes of zeros past the last row (gathers read
+    // a row group's full width at any row)
+    const size_t f32_bytes = sizeof(float) * n * ld32;
+    if (hipMalloc(&ix->base_f32, f32_bytes + kRowTailBytes) != hipSuccess ||
         hipMalloc(&ix->graph, sizeof(uint32_t) * n * ix->R_pad) != hipSuccess)
         return cleanup(fail(NSG_ENOMEM, "device allocation of the index failed"));
-    hipError_t e = hipSuccess;
-    if (ld32 != d) e = hipMemsetAsync(ix->base_f32, 0, sizeof(float) * n * ld32, st);
+    hipError_t e = hipMemsetAsync((char *)ix->base_f32 + f32_bytes, 0, kRowTailBytes, st);
+    if (e == hipSuccess && ld32 != d) e = hipMemsetAsync(ix->base_f32, 0, f32_bytes, st);
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(ix->base_f32, sizeof(float) * ld32, base, sizeof(float) * d,
                              sizeof(float) * d, n, hipMemcpyDeviceToDevice, st);
@@ -235,8 +238,11 @@ extern "C" int nsg_load_index(const float *base, int64_t n, int32_t d, const uin
         }
         const int row_elems = ix->row_chunks * epc;
         const size_t esz = storage == NSG_E4M3 ? 1 : 2;
-        if (hipMalloc(&ix->base_lp, esz * n * row_elems) != hipSuccess)
+        const size_t lp_bytes = esz * n * row_elems;
+        if (hipMalloc(&ix->base_lp, lp_bytes + kRowTailBytes) != hipSuccess)
             return cleanup(fail(NSG_ENOMEM, "alloc of reduced rows failed"));
+        if (hipMemsetAsync((char *)ix->base_lp + lp_bytes, 0, kRowTailBytes, st) != hipSuccess)
+            return cleanup(fail(NSG_EDEVICE, "clearing the row tail failed"));
         hipLaunchKernelGGL(encode_kernel, dim3(grid_for(n * row_elems)), dim3(256), 0, st, ix->base_f32, n, d,
                            ld32, ix->scales, (int)storage, ix->base_lp, row_elems);
     }
@@ -312,7 +318,8 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
         return fail(NSG_EINVAL, "hash_slots must be a power of two");
     if (o.hash_slots && (o.hash_slots < 64 || o.hash_slots > 16384))
         return fail(NSG_EINVAL, "hash_slots out of range [64, 16384]");
-    if (o.waves_per_block < 0 || o.waves_per_block > 16) return fail(NSG_EINVAL, "waves_per_block out of range");
+    if (o.waves_per_block < 0 || o.waves_per_block > 4)
+        return fail(NSG_EINVAL, "waves_per_block=%d out of range [0, 4]", o.waves_per_block);
     if (o.pool_ids && (o.pool_stride < 1 || !o.pool_dist)) return fail(NSG_EINVAL, "pool output needs stride and dist");
     if (o.learned_stop < 0 || o.learned_stop > 1) return fail(NSG_EINVAL, "learned_stop must be 0 or 1");
     if (o.learned_stop && !stop_ready(idx)) return fail(NSG_ESTATE, "no early-stop model loaded and enabled");
@@ -350,6 +357,7 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.nedges = o.nedges;
     a.lanes_per_row = o.lanes_per_row;
     a.counter = o.counter;
+    a.clamped = o.clamped;
     a.pool_ids = o.pool_ids;
     a.pool_dist = o.pool_dist;
     a.pool_stride = o.pool_stride;
@@ -367,6 +375,9 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
                                    int32_t hop, int32_t grid_n) {
     clear_error();
     if (!idx || !blob) return fail(NSG_EINVAL, "NULL index or blob");
+    if (idx->stop_graphs.load() > 0)
+        return fail(NSG_ESTATE, "%d search graph(s) captured with the early stop still use the model",
+                    idx->stop_graphs.load());
     if (in != kStopFeatures) return fail(NSG_EINVAL, "model input %d must be %d features", in, kStopFeatures);
     if (h < 1 || h > 64) return fail(NSG_EUNSUPPORTED, "hidden width %d outside [1, 64]", h);
     if (hop < 1) return fail(NSG_EINVAL, "hop must be >= 1");
@@ -421,6 +432,9 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
 extern "C" int nsg_set_stop_mode(nsg_index *idx, int32_t enabled, float calib_c) {
     clear_error();
     if (!idx) return fail(NSG_EINVAL, "index is NULL");
+    if (idx->stop_graphs.load() > 0)
+        return fail(NSG_ESTATE, "%d search graph(s) captured with the early stop hold its calibration",
+                    idx->stop_graphs.load());
     if (enabled && !idx->stop.blob) return fail(NSG_ESTATE, "no early-stop model loaded");
     if (!(calib_c > 0.0f) || !std::isfinite(calib_c)) return fail(NSG_EINVAL, "calibration must be finite and > 0");
     idx->stop.enabled = enabled ? 1 : 0;
@@ -435,6 +449,7 @@ struct nsg_search_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     unsigned int *counter = nullptr;
+    const nsg_index *stop_idx = nullptr;   // index whose early-stop model the graph holds
 };
 
 extern "C" void nsg_search_graph_destroy(nsg_search_graph *g) {
@@ -443,6 +458,7 @@ extern "C" void nsg_search_graph_destroy(nsg_search_graph *g) {
     if (g->exec) hipGraphExecDestroy(g->exec);
     if (g->graph) hipGraphDestroy(g->graph);
     hipFree(g->counter);
+    if (g->stop_idx) g->stop_idx->stop_graphs.fetch_sub(1);
     delete g;
 }
 
@@ -486,6 +502,10 @@ extern "C" int nsg_search_graph_create(const nsg_index *idx, const float *querie
     if (rc != NSG_OK) {
         nsg_search_graph_destroy(g);
         return rc;
+    }
+    if (o.learned_stop) {
+        g->stop_idx = idx;
+        idx->stop_graphs.fetch_add(1);
     }
     *out = g;
     return NSG_OK;

@@ -45,21 +45,34 @@ struct BFParams {
 
 __device__ inline void bsync() { __syncthreads(); }
 
-// column sums in FP64: block b takes rows b, b + gridDim.x, ...; threads walk
-// the dimensions of a row (coalesced), then add into acc[d]
-__global__ void colsum_kernel(const float *x, int64_t n, int d, double *acc) {
+// Column means in FP32 with compensated (Neumaier) sums: block b takes rows
+// b, b + gridDim.x, ... and writes its partial sum and compensation per
+// column; mean_finish_kernel adds the partials in block order, so the result
+// is deterministic and close to the correctly rounded mean.
+__global__ void colsum_part_kernel(const float *x, int64_t n, int d, float2 *part) {
     for (int j0 = 0; j0 < d; j0 += blockDim.x) {
-        int j = j0 + threadIdx.x;
-        double s = 0.0;
-        if (j < d)
-            for (int64_t i = blockIdx.x; i < n; i += gridDim.x) s += (double)x[i * d + j];
-        if (j < d) atomicAdd(&acc[j], s);
+        const int j = j0 + threadIdx.x;
+        if (j >= d) continue;
+        float s = 0.0f, c = 0.0f;
+        for (int64_t i = blockIdx.x; i < n; i += gridDim.x) neumaier_add(s, c, x[i * d + j]);
+        part[(size_t)blockIdx.x * d + j] = make_float2(s, c);
     }
 }
 
-__global__ void mean_finish_kernel(const double *acc, int64_t n, int d, float *mu) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < d) mu[j] = (float)(acc[j] / (double)n);
+__global__ void mean_finish_kernel(const float2 *part, int nblk, int64_t n, int d, float *mu) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d) return;
+    float s = 0.0f, c = 0.0f;
+    for (int b = 0; b < nblk; ++b) {
+        const float2 p = part[(size_t)b * d + j];
+        neumaier_add(s, c, p.x);
+        c += p.y;
+    }
+    // (s + c) / n with the rounding error of s / n carried into the quotient
+    const float fn = (float)n;
+    const float q0 = s / fn;
+    const float r = fmaf(-q0, fn, s);   // s - q0 * n (exact when n < 2^24)
+    mu[j] = q0 + (r + c) / fn;
 }
 
 __global__ void cnorm_kernel(const float *x, int64_t n, int d, const float *mu, float *out) {
@@ -285,10 +298,13 @@ __global__ void __launch_bounds__(256) bf_rerank_kernel(const float *base, const
     }
 }
 
-int launch_mean(const float *x, int64_t n, int d, float *mu, double *acc, hipStream_t st) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)std::min<int64_t>(n, 1024)), dim3(d < 256 ? (d + 63) / 64 * 64 : 256),
-                       0, st, x, n, d, acc);
-    hipLaunchKernelGGL(mean_finish_kernel, dim3((d + 255) / 256), dim3(256), 0, st, acc, n, d, mu);
+int mean_blocks(int64_t n) { return (int)std::min<int64_t>(n, 256); }
+
+int launch_mean(const float *x, int64_t n, int d, float *mu, float2 *part, hipStream_t st) {
+    const int nblk = mean_blocks(n);
+    hipLaunchKernelGGL(colsum_part_kernel, dim3((unsigned)nblk), dim3(d < 256 ? (d + 63) / 64 * 64 : 256), 0, st,
+                       x, n, d, part);
+    hipLaunchKernelGGL(mean_finish_kernel, dim3((d + 255) / 256), dim3(256), 0, st, part, nblk, n, d, mu);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(NSG_EDEVICE, "mean kernels failed: %s", hipGetErrorString(e));
     return NSG_OK;
@@ -328,11 +344,10 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     while (sort_n < ncand) sort_n <<= 1;
     if (sort_n * 8 > 64 * 1024) return fail(NSG_EUNSUPPORTED, "too many candidates per query (%d)", ncand);
     float *mu = nullptr, *xnorm = nullptr, *qnorm = nullptr;
-    double *acc = nullptr;
+    float2 *acc = nullptr;
     uint32_t *cand = nullptr;
     uint64_t *cbuf = nullptr;
-    NSG_HIP(hipMallocAsync((void **)&acc, sizeof(double) * d, st));
-    NSG_HIP(hipMemsetAsync(acc, 0, sizeof(double) * d, st));
+    NSG_HIP(hipMallocAsync((void **)&acc, sizeof(float2) * d * mean_blocks(n), st));
     NSG_HIP(hipMallocAsync((void **)&mu, sizeof(float) * d, st));
     NSG_HIP(hipMallocAsync((void **)&xnorm, sizeof(float) * n, st));
     NSG_HIP(hipMallocAsync((void **)&qnorm, sizeof(float) * nq, st));

@@ -23,7 +23,7 @@
 namespace nsg {
 
 struct SelParams {
-    const uint4 *rows;       // FP32 rows, stride row_chunks
+    RowTable tab;            // FP32 rows of the index copy
     int row_chunks;
     uint32_t n_rows;
     const uint32_t *vis_ids;
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelParams p) {
         const float dvp = key_dist(pk);
         bool conflict = false;
         if (s > 0) {
-            const uint4 *prow = p.rows + (int64_t)pid * p.row_chunks;
+            const uint4 *prow = reinterpret_cast<const uint4 *>(p.tab.base) + (int64_t)pid * p.row_chunks;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 int ch = li + c * LPR;
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelParams p) {
 #pragma unroll
                 for (int e = 0; e < EPC; ++e) sc[c][e] = 0.0f;
             }
-            gather_dist<NSG_F32, LPR, CPL>(p.rows, p.row_chunks, p.n_rows, qv, sc, sel, cdist, s, lane);
+            gather_dist<NSG_F32, LPR, CPL>(p.tab, qv, sc, sel, cdist, s, lane);
             wave_sync();
             bool c0 = lane < s && cdist[lane] < dvp;
             bool c1 = lane + 64 < s && cdist[lane + 64] < dvp;
@@ -184,9 +184,10 @@ extern "C" int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t
     };
     // 1. centroid
     float *cen = nullptr;
-    double *acc = nullptr;
-    if ((rc = dalloc((void **)&cen, sizeof(float) * d)) || (rc = dalloc((void **)&acc, sizeof(double) * d))) return rc;
-    NSG_HIP(hipMemsetAsync(acc, 0, sizeof(double) * d, st));
+    float2 *acc = nullptr;
+    if ((rc = dalloc((void **)&cen, sizeof(float) * d)) ||
+        (rc = dalloc((void **)&acc, sizeof(float2) * d * mean_blocks(n))))
+        return rc;
     rc = launch_mean(base, n, d, cen, acc, st);
     if (rc) return rc;
     // 2. navigating node
@@ -230,7 +231,10 @@ extern "C" int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t
     int C_alloc = 1;
     while (C_alloc < C) C_alloc <<= 1;
     SelParams sp{};
-    sp.rows = reinterpret_cast<const uint4 *>(kix->base_f32);
+    sp.tab.base = reinterpret_cast<const unsigned char *>(kix->base_f32);
+    sp.tab.row_bytes = (uint32_t)kix->row_chunks_f32 * 16u;
+    sp.tab.n_rows = (uint32_t)n;
+    sp.tab.row_chunks = kix->row_chunks_f32;
     sp.row_chunks = kix->row_chunks_f32;
     sp.n_rows = (uint32_t)n;
     sp.vis_ids = vid;

@@ -4,6 +4,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <atomic>
+
 #include "../../include/nsg.h"
 
 #define NSG_SENT 0xFFFFFFFFu
@@ -15,6 +17,9 @@ constexpr int kMaxR = 128;
 constexpr int kMaxK = 512;
 constexpr int kMaxD = 1024;
 constexpr int kWave = 64;
+// zero bytes every row table carries past its last row: the widest gather
+// layout (64 lanes x 4 chunks of 16 bytes) may read that far
+constexpr int kRowTailBytes = 64 * 4 * 16;
 
 // ---- error reporting (thread-local message) -------------------------------
 int fail(int code, const char *fmt, ...);
@@ -57,6 +62,9 @@ struct nsg_index {
     uint32_t *graph = nullptr;   // [n][R_pad]
     int device = 0;
     nsg::StopModel stop;
+    // live search graphs captured with the early stop (they hold the model's
+    // device pointer and calibration as captured)
+    mutable std::atomic<int> stop_graphs{0};
 };
 
 namespace nsg {
@@ -87,7 +95,8 @@ struct SearchArgs {
     int64_t *nedges;          // valid neighbour entries read, summed over expansions
     int32_t feature_hop;      // decision / trace hop (0: 16)
     int32_t lanes_per_row;    // 0: default layout
-    unsigned int *counter;    // persistent work counter (NULL: allocated per call)
+    unsigned int *counter;    // persistent work counter (NULL: the calling stream's library counter)
+    int32_t *clamped;         // queries whose k[i] / L[i] were clamped (device counter), or NULL
     int32_t *budget;
     int32_t max_hops;
     float *features;
@@ -106,13 +115,26 @@ struct SearchArgs {
     int32_t *vis_cnt;
     int32_t vis_cap;
     int64_t self_offset;      // >= 0: query i is base row self_offset + i (index build), else -1
+    // partitioned index: nq counts (query, shard) searches, search i is query
+    // i / shards in shard i % shards from shard_starts[i % shards] (device)
+    int32_t shards;           // 0 or 1: one graph
+    const uint32_t *shard_starts;
     hipStream_t stream;
 };
 
 int launch_search(const SearchArgs &a);
 
-// FP32 mean of the rows of x[n][d] (FP64 sums; acc[d] must be zeroed)
-int launch_mean(const float *x, int64_t n, int d, float *mu, double *acc, hipStream_t st);
+// FP32 mean of the rows of x[n][d] (compensated FP32 sums); part holds
+// mean_blocks(n) * d partial sums
+int mean_blocks(int64_t n);
+int launch_mean(const float *x, int64_t n, int d, float *mu, float2 *part, hipStream_t st);
+
+// compensated (Neumaier) summation step: s + c tracks the exact running sum
+__device__ inline void neumaier_add(float &s, float &c, float v) {
+    const float t = s + v;
+    c += fabsf(s) >= fabsf(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+}
 
 // visited-filter size (log2 slots) used for a pool of L entries
 int default_hash_bits(int L);

@@ -169,27 +169,34 @@ __global__ void recall_hits_kernel(const uint32_t *found, int64_t nq, int G, int
     hits[t] = c;
 }
 
-// per-column mean and 1/std (FP64 sums; std floored at 1e-12 of the mean
-// magnitude and 1e-30), one thread per column, rows in order (deterministic).
+// per-column mean and 1/std, one thread per column, rows in order
+// (deterministic), two passes of compensated FP32 sums (mean, then the mean
+// squared deviation); std floored at 1e-12 of the mean magnitude and 1e-30.
 // NaN rows (searches that ended before the feature hop) are skipped.
 __global__ void column_stats_kernel(const float *X, int64_t B, int in, float *mean, float *inv_std) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= in) return;
-    double s = 0.0, s2 = 0.0;
-    int64_t c = 0;
+    float s = 0.0f, cs = 0.0f;
+    int64_t cnt = 0;
     for (int64_t b = 0; b < B; ++b) {
-        float v = X[b * in + j];
+        const float v = X[b * in + j];
         if (isnan(v)) continue;
-        s += v;
-        s2 += (double)v * v;
-        ++c;
+        neumaier_add(s, cs, v);
+        ++cnt;
     }
-    double m = c ? s / (double)c : 0.0;
-    double var = c ? s2 / (double)c - m * m : 0.0;
-    double sd = sqrt(var > 0.0 ? var : 0.0);
-    double floor_ = fmax(1e-12 * fabs(m), 1e-30);
-    mean[j] = (float)m;
-    inv_std[j] = (float)(1.0 / (sd > floor_ ? sd : 1.0));
+    const float m = cnt ? (s + cs) / (float)cnt : 0.0f;
+    float q = 0.0f, cq = 0.0f;
+    for (int64_t b = 0; b < B; ++b) {
+        const float v = X[b * in + j];
+        if (isnan(v)) continue;
+        const float dv = v - m;
+        neumaier_add(q, cq, dv * dv);
+    }
+    const float var = cnt ? (q + cq) / (float)cnt : 0.0f;
+    const float sd = sqrtf(var > 0.0f ? var : 0.0f);
+    const float floor_ = fmaxf(1e-12f * fabsf(m), 1e-30f);
+    mean[j] = m;
+    inv_std[j] = 1.0f / (sd > floor_ ? sd : 1.0f);
 }
 
 static int mlp_rows(const float *params, int in, int h, const float *X, const float *y, int64_t B, float *yhat,

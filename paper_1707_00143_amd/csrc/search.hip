@@ -4,6 +4,9 @@
 #include "search_impl.hpp"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace nsg {
 
@@ -21,6 +24,29 @@ void pick_layout(int chunks, int max_cpl, int *lpr, int *cpl) {
 }
 
 __global__ void reset_counter_kernel(unsigned int *c) { if (threadIdx.x == 0) c[0] = 0u; }
+
+// Work counter of the persistent grid for calls that bring none: one per
+// (device, stream), allocated on first use and kept for the life of the
+// process.  Launches on one stream run in order, so they can share it; calls
+// on different streams get different counters.
+static int stream_counter(hipStream_t st, unsigned int **out) {
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, unsigned int *> counters;
+    int dev = 0;
+    NSG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(dev, st);
+    auto it = counters.find(key);
+    if (it != counters.end()) {
+        *out = it->second;
+        return NSG_OK;
+    }
+    unsigned int *c = nullptr;
+    if (hipMalloc((void **)&c, 256) != hipSuccess) return fail(NSG_ENOMEM, "work counter allocation failed");
+    counters[key] = c;
+    *out = c;
+    return NSG_OK;
+}
 
 kfn_t pick_search_kernel_f32(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_f32_stop(int lpr, int cpl, int nch);
@@ -41,7 +67,10 @@ int launch_search(const SearchArgs &a) {
     if (a.nq == 0) return NSG_OK;
     KParams p{};
     const bool lp = ix->storage != NSG_F32;
-    p.rows = reinterpret_cast<const uint4 *>(lp ? ix->base_lp : (const void *)ix->base_f32);
+    p.tab.base = reinterpret_cast<const unsigned char *>(lp ? ix->base_lp : (const void *)ix->base_f32);
+    p.tab.row_bytes = (uint32_t)ix->row_chunks * 16u;
+    p.tab.n_rows = (uint32_t)ix->n;
+    p.tab.row_chunks = ix->row_chunks;
     p.scales = ix->scales;
     p.rows_f32 = ix->base_f32;
     p.graph = a.graph_override ? a.graph_override : ix->graph;
@@ -68,6 +97,7 @@ int launch_search(const SearchArgs &a) {
     p.ndist = a.ndist;
     p.nedges = a.nedges;
     p.max_hops = a.max_hops;
+    p.clamped = a.clamped;
     p.pool_ids = a.pool_ids;
     p.pool_dist = a.pool_dist;
     p.pool_stride = a.pool_stride;
@@ -76,6 +106,8 @@ int launch_search(const SearchArgs &a) {
     p.vis_cnt = a.vis_cnt;
     p.vis_cap = a.vis_cap;
     p.self_offset = a.self_offset;
+    p.shards = a.shards > 1 ? a.shards : 1;
+    p.shard_starts = a.shard_starts;
     // learned early stop and feature capture, fused into the search loop
     p.features = a.features;
     p.budget = a.budget;
@@ -143,14 +175,13 @@ int launch_search(const SearchArgs &a) {
     size_t lds = per_wave * wpb;
     if (lds > 64 * 1024) NSG_HIP(hipFuncSetAttribute((const void *)fn,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    unsigned int *counter = nullptr;
     int64_t blocks;
     if (a.persistent) {
         if (a.counter) {
             p.counter = a.counter;
         } else {
-            NSG_HIP(hipMallocAsync((void **)&counter, sizeof(unsigned int) * 64, a.stream));
-            p.counter = counter;
+            int rc = stream_counter(a.stream, &p.counter);
+            if (rc) return rc;
         }
         hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, a.stream, p.counter);
         int per_cu = 0;
@@ -168,10 +199,6 @@ int launch_search(const SearchArgs &a) {
     }
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, p);
     hipError_t e = hipGetLastError();
-    if (counter) {
-        hipError_t e2 = hipFreeAsync(counter, a.stream);
-        if (e == hipSuccess) e = e2;
-    }
     if (e != hipSuccess) return fail(NSG_EDEVICE, "search launch failed: %s", hipGetErrorString(e));
     return NSG_OK;
 }

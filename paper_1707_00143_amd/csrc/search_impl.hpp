@@ -6,7 +6,7 @@
 namespace nsg {
 
 struct KParams {
-    const uint4 *rows;           // search-format rows, stride row_chunks
+    RowTable tab;                // search-format rows (row_chunks chunks each)
     const float *scales;         // [row_chunks * EPC] (reduced formats)
     const float *rows_f32;       // FP32 rows for re-ranking, stride row_chunks_f32 * 4
     const uint32_t *graph;
@@ -23,6 +23,7 @@ struct KParams {
     int L_cap, L_alloc, hash_bits, lds_per_wave;
     int rerank;
     unsigned int *counter;
+    int32_t *clamped;            // queries whose k / L were clamped into range, or NULL
     int64_t *hops, *ndist, *nedges;
     int max_hops;                // expansion budget for every query (0: none)
     uint32_t *pool_ids;
@@ -33,6 +34,10 @@ struct KParams {
     int32_t *vis_cnt;
     int vis_cap;
     int64_t self_offset;         // >= 0: query i is base row self_offset + i; its own row is visited at the end
+    // partitioned index: search i is query i / shards in shard i % shards,
+    // started at shard_starts[i % shards] (shards = 1: one graph, `start`)
+    int shards;
+    const uint32_t *shard_starts;
     // learned early stop, fused into the search loop (see stop_decide)
     const float *stop_plan;      // network (kernel layout, see stop_decide)
     int32_t *budget;             // chosen budget per query (0: none), or NULL
@@ -221,10 +226,13 @@ search_kernel(KParams p) {
         qi = (int64_t)blockIdx.x * wpb + wave;
     }
     while (qi < p.nq) {
-        const float *q = p.queries + qi * (int64_t)p.d;
+        const int64_t qrow = p.shards > 1 ? qi / p.shards : qi;
+        const float *q = p.queries + qrow * (int64_t)p.d;
         int kq = p.k_arr ? p.k_arr[qi] : p.k_scalar;
-        kq = kq < 0 ? 0 : (kq > p.out_stride ? p.out_stride : kq);
         int Lq = p.L_arr ? p.L_arr[qi] : p.L_scalar;
+        if (p.clamped && lane == 0 && (kq < 0 || kq > p.out_stride || Lq < 1 || Lq > p.L_cap))
+            atomicAdd(p.clamped, 1);
+        kq = kq < 0 ? 0 : (kq > p.out_stride ? p.out_stride : kq);
         Lq = Lq < 1 ? 1 : (Lq > p.L_cap ? p.L_cap : Lq);
         const int Lcur = Lq;
         // expansion budget: the caller's, and after the decision hop the
@@ -254,7 +262,7 @@ search_kernel(KParams p) {
         for (int i = lane; i < H; i += 64) hash[i] = NSG_SENT;
         wave_sync();
 
-        const uint32_t start = p.start;
+        const uint32_t start = p.shards > 1 ? p.shard_starts[qi % p.shards] : p.start;
         int64_t hops = 0, nd = 0, ne = 0;
         int vcount = 0;
         const bool rec = FULL && p.vis_ids != nullptr;
@@ -262,7 +270,7 @@ search_kernel(KParams p) {
         // pool <- {start}
         if (lane == 0) { cid[0] = start; hash_insert(hash, p.hash_bits, start); }
         wave_sync();
-        gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, p.n_rows, qv, sc, cid, cdist, 1, lane);
+        gather_dist<DT, LPR, CPL>(p.tab, qv, sc, cid, cdist, 1, lane);
         wave_sync();
         nd = 1;
         if (rec && lane == 0 && vcount < p.vis_cap) {
@@ -301,7 +309,7 @@ search_kernel(KParams p) {
             wave_sync();
             nd += cnt;
             if (cnt > 0) {
-                gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, p.n_rows, qv, sc, cid, cdist, cnt, lane);
+                gather_dist<DT, LPR, CPL>(p.tab, qv, sc, cid, cdist, cnt, lane);
                 wave_sync();
                 if (rec) {
                     for (int r = lane; r < cnt; r += 64)
@@ -351,7 +359,7 @@ search_kernel(KParams p) {
             }
             wave_sync();
             if (cnt > 0) {
-                gather_dist<DT, LPR, CPL>(p.rows, p.row_chunks, p.n_rows, qv, sc, cid, cdist, cnt, lane);
+                gather_dist<DT, LPR, CPL>(p.tab, qv, sc, cid, cdist, cnt, lane);
                 wave_sync();
                 if (rec)
                     for (int r = lane; r < cnt; r += 64)

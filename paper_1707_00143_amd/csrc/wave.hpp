@@ -43,19 +43,9 @@ template <> struct Fmt<NSG_F16> {
         }
     }
 };
-// OCP FP8 E4M3 (bias 7, no infinities, S.1111.111 is NaN), decoded from its fields
-__device__ inline float e4m3_to_f32(uint32_t b) {
-    uint32_t s = (b & 0x80u) << 24;
-    uint32_t e = (b >> 3) & 0xFu;
-    uint32_t m = b & 7u;
-    float nrm = __uint_as_float(((e + 120u) << 23) | (m << 20));
-    float sub = (float)m * 0x1p-9f;
-    float v = e ? nrm : sub;
-    v = (e == 15u && m == 7u) ? __uint_as_float(0x7FC00000u) : v;
-    return __uint_as_float(__float_as_uint(v) | s);
-}
-// The packed hardware conversion decodes OCP E4M3 exactly as e4m3_to_f32
-// does (checked on all 256 codes on gfx950), two bytes per instruction.
+// OCP FP8 E4M3 (bias 7, no infinities, S.1111.111 is NaN) by the packed
+// hardware conversion, two bytes per instruction (it equals the field-by-field
+// definition on all 256 codes, checked on gfx950 by a GPU test).
 template <> struct Fmt<NSG_E4M3> {
     static constexpr int EPC = 16;
     __device__ static inline void dec(const uint4 r, float *o) {
@@ -84,12 +74,6 @@ __device__ inline void wave_sync() {
     asm volatile("" ::: "memory");
 }
 
-__device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
-    uint32_t lo = __shfl_xor((unsigned int)(v & 0xFFFFFFFFu), m);
-    uint32_t hi = __shfl_xor((unsigned int)(v >> 32), m);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 __device__ inline uint64_t mk_key(float d, uint32_t id) {
     return ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)id;
 }
@@ -115,23 +99,6 @@ __device__ inline float group_sum(float s) {
     return s;
 }
 
-// ascending bitonic sort of one key per lane across the 64 lanes
-__device__ inline uint64_t wave_sort64(uint64_t key, int lane) {
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            uint64_t o = shfl_xor64(key, j);
-            bool up = (lane & k) == 0;
-            bool lower = (lane & j) == 0;
-            uint64_t mn = key < o ? key : o;
-            uint64_t mx = key < o ? o : key;
-            key = (lower == up) ? mn : mx;
-        }
-    }
-    return key;
-}
-
 // Visited filter: a direct-mapped table of node ids.  Exchanging u into its
 // slot returns the previous occupant: u itself means u was seen; anything else
 // means it was not (or was evicted by a colliding id, i.e. forgotten, which
@@ -139,26 +106,6 @@ __device__ inline uint64_t wave_sort64(uint64_t key, int lane) {
 __device__ inline bool hash_insert(uint32_t *tab, int bits, uint32_t u) {
     const uint32_t h = (u * 2654435761u) >> (32 - bits);
     return atomicExch(&tab[h], u) != u;
-}
-
-// index of the first unchecked pool entry at or after `from`, -1 if none
-__device__ inline int find_unchecked(const uint64_t *pool, int from, int size, int lane) {
-    for (int b = from; b < size; b += 64) {
-        int i = b + lane;
-        bool unc = i < size && !(pool[i] & CHECKED_BIT);
-        uint64_t bm = __ballot(unc);
-        if (bm) return b + __ffsll((long long)bm) - 1;
-    }
-    return -1;
-}
-
-__device__ inline int lower_bound_pool(const uint64_t *pool, int size, uint64_t key) {
-    int lo = 0, hi = size;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if ((pool[mid] & KEY_MASK) < key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
 }
 
 __device__ inline uint64_t readlane64(uint64_t v, int l) {
@@ -390,16 +337,6 @@ __device__ __attribute__((always_inline)) inline bool rp_insert(RegPool<NCH> &P,
     return true;
 }
 
-// drop entries at or beyond n
-template <int NCH>
-__device__ __attribute__((always_inline)) inline void rp_truncate(RegPool<NCH> &P, int n, int lane) {
-    if (P.size <= n) return;
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-        if ((c << 6) + lane >= n) P.pk[c] = KEY_NONE;
-    P.size = n;
-}
-
 // write the pool to LDS (checked flag in the key's flag bit)
 template <int NCH>
 __device__ __attribute__((always_inline)) inline void rp_store(const RegPool<NCH> &P, uint64_t *pool, int lane) {
@@ -411,6 +348,18 @@ __device__ __attribute__((always_inline)) inline void rp_store(const RegPool<NCH
     }
 }
 
+// Rows the gathers read: n_rows rows of row_chunks 16-byte chunks each.  The
+// allocation extends kRowTailBytes (zero-filled) past the last row, so every
+// lane of a row group may read its full width of chunks at any row, also
+// where the row holds fewer chunks (those reads are discarded, see
+// gather_dist) without a per-lane condition on the load.
+struct RowTable {
+    const unsigned char *base;
+    uint32_t row_bytes;   // row_chunks * 16
+    uint32_t n_rows;
+    int row_chunks;
+};
+
 // rows of one gather round
 template <int LPR, int CPL>
 struct GatherShape {
@@ -419,56 +368,45 @@ struct GatherShape {
     static constexpr int ROWS = RPP * U;
 };
 
-// One gather round, split in two so that other work can run while its loads
-// are in flight.  gather_issue reads the row ids cid[r], r = r0 + u * RPP +
-// lane / LPR (u < U), in one LDS round trip and issues every row load (rows at
-// or beyond cnt are not loaded); gather_finish turns the loaded chunks into
-// squared distances to q, which every lane of a row group receives.
-template <int DT, int LPR, int CPL>
-struct GatherRaw {
-    uint4 raw[GatherShape<LPR, CPL>::U][CPL];
-    uint32_t ids[GatherShape<LPR, CPL>::U];
-};
-
-template <int DT, int LPR, int CPL>
-__device__ __attribute__((always_inline)) inline void gather_issue(const uint4 *rows, int row_chunks,
-                                                                   uint32_t n_rows, const uint32_t *cid, int r0,
-                                                                   int cnt, int lane, GatherRaw<DT, LPR, CPL> &G) {
-    constexpr int RPP = GatherShape<LPR, CPL>::RPP;
-    constexpr int U = GatherShape<LPR, CPL>::U;
-    const int g = lane / LPR, li = lane % LPR;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int r = r0 + u * RPP + g;
-        G.ids[u] = cid[r < kMaxR ? r : kMaxR - 1];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const bool ok = r0 + u * RPP + g < cnt;
-        const uint32_t iu = G.ids[u] < n_rows ? G.ids[u] : 0u;     // never index past the base
-        const uint4 *row = rows + (int64_t)iu * row_chunks;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            int ch = li + c * LPR;
-            G.raw[u][c] = (ok && ch < row_chunks) ? row[ch] : make_uint4(0u, 0u, 0u, 0u);
-        }
-    }
-}
-
-template <int DT, int LPR, int CPL>
-__device__ __attribute__((always_inline)) inline void gather_finish(const float (&qv)[CPL][Fmt<DT>::EPC],
-                                                                    const float (&sc)[CPL][Fmt<DT>::EPC],
-                                                                    const GatherRaw<DT, LPR, CPL> &G,
-                                                                    float (&dist)[GatherShape<LPR, CPL>::U]) {
+// One round of NP passes of the gather: the row ids of the round are read
+// from LDS and every row load is issued, then the passes are reduced (straight
+// line code, so the loads of all passes are in flight together).  A lane
+// whose row lies past the last one (r >= cnt) re-reads the last row, so no
+// load needs a per-lane condition; its distance is not stored.  Chunks beyond
+// a row's end contribute nothing: reduced formats carry a zero scale and a
+// zero query there, FP32 rows (`part`) are zeroed explicitly.
+template <int DT, int LPR, int CPL, int NP>
+__device__ __attribute__((always_inline)) inline void gather_round(const RowTable &T, const unsigned char *lane_base,
+                                                                   const float (&qv)[CPL][Fmt<DT>::EPC],
+                                                                   const float (&sc)[CPL][Fmt<DT>::EPC],
+                                                                   const uint32_t *cid, float *cdist, int r0,
+                                                                   int cnt, int lane, bool part) {
     constexpr int EPC = Fmt<DT>::EPC;
-    constexpr int U = GatherShape<LPR, CPL>::U;
+    constexpr int RPP = GatherShape<LPR, CPL>::RPP;
+    const int g = lane / LPR, li = lane % LPR;
+    uint4 raw[NP][CPL];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < NP; ++u) {
+        int r = r0 + u * RPP + g;
+        r = r < cnt ? r : cnt - 1;
+        uint32_t id = cid[r];
+        id = id < T.n_rows ? id : 0u;   // never index past the table
+        const unsigned char *rp = lane_base + (uint64_t)id * T.row_bytes;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) raw[u][c] = *reinterpret_cast<const uint4 *>(rp + c * LPR * 16);
+    }
+    // keep the reductions below every load of the round (the scheduler would
+    // otherwise start one and wait for its data before the last loads issue)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
         float acc = 0.0f;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
+            uint4 v = raw[u][c];
+            if (part && li + c * LPR >= T.row_chunks) v = make_uint4(0u, 0u, 0u, 0u);
             float x[EPC];
-            Fmt<DT>::dec(G.raw[u][c], x);
+            Fmt<DT>::dec(v, x);
 #pragma unroll
             for (int e = 0; e < EPC; ++e) {
                 float xv = DT == NSG_F32 ? x[e] : sc[c][e] * x[e];
@@ -476,37 +414,36 @@ __device__ __attribute__((always_inline)) inline void gather_finish(const float 
                 acc = fmaf(t, t, acc);
             }
         }
-        dist[u] = group_sum<LPR>(acc);
+        const float dsum = group_sum<LPR>(acc);
+        const int r = r0 + u * RPP + g;
+        if (li == 0 && r < cnt) cdist[r] = dsum;
     }
 }
 
-// distances of one round -> cdist[r] (one lane per row)
-template <int LPR, int CPL>
-__device__ __attribute__((always_inline)) inline void store_round(const float (&dist)[GatherShape<LPR, CPL>::U],
-                                                                  float *cdist, int r0, int cnt, int lane) {
+// Squared distances of q to the rows cid[0..cnt) -> cdist[0..cnt) (cnt >= 1).
+// LPR lanes gather one row (lane li of the group reads chunks li + c * LPR,
+// c < CPL, at compile-time offsets from one row address); a pass covers RPP
+// rows.  Rounds take U passes while enough rows are left; the last round
+// takes the fewest passes (1, 2, 4 or U) that cover its rows.
+template <int DT, int LPR, int CPL>
+__device__ inline void gather_dist(const RowTable &T, const float (&qv)[CPL][Fmt<DT>::EPC],
+                                   const float (&sc)[CPL][Fmt<DT>::EPC], const uint32_t *cid, float *cdist,
+                                   int cnt, int lane) {
     constexpr int RPP = GatherShape<LPR, CPL>::RPP;
     constexpr int U = GatherShape<LPR, CPL>::U;
-    const int g = lane / LPR, li = lane % LPR;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int r = r0 + u * RPP + g;
-        if (li == 0 && r < cnt) cdist[r] = dist[u];
-    }
-}
-
-// squared distances of q to the rows cid[0..cnt) (search format) -> cdist
-template <int DT, int LPR, int CPL>
-__device__ inline void gather_dist(const uint4 *rows, int row_chunks, uint32_t n_rows,
-                                   const float (&qv)[CPL][Fmt<DT>::EPC],
-                                   const float (&sc)[CPL][Fmt<DT>::EPC],
-                                   const uint32_t *cid, float *cdist, int cnt, int lane) {
-    constexpr int ROWS = GatherShape<LPR, CPL>::ROWS;
-    for (int r0 = 0; r0 < cnt; r0 += ROWS) {
-        GatherRaw<DT, LPR, CPL> G;
-        float dist[GatherShape<LPR, CPL>::U];
-        gather_issue<DT, LPR, CPL>(rows, row_chunks, n_rows, cid, r0, cnt, lane, G);
-        gather_finish<DT, LPR, CPL>(qv, sc, G, dist);
-        store_round<LPR, CPL>(dist, cdist, r0, cnt, lane);
+    constexpr int U2 = U < 2 ? U : 2, U4 = U < 4 ? U : 4;
+    const unsigned char *lane_base = T.base + (lane % LPR) * 16;
+    const bool part = DT == NSG_F32 && LPR * CPL > T.row_chunks;   // wave-uniform
+    for (int r0 = 0; r0 < cnt; r0 += U * RPP) {
+        const int left = cnt - r0;
+        if (left <= RPP)
+            gather_round<DT, LPR, CPL, 1>(T, lane_base, qv, sc, cid, cdist, r0, cnt, lane, part);
+        else if (U > 2 && left <= 2 * RPP)
+            gather_round<DT, LPR, CPL, U2>(T, lane_base, qv, sc, cid, cdist, r0, cnt, lane, part);
+        else if (U > 4 && left <= 4 * RPP)
+            gather_round<DT, LPR, CPL, U4>(T, lane_base, qv, sc, cid, cdist, r0, cnt, lane, part);
+        else
+            gather_round<DT, LPR, CPL, U>(T, lane_base, qv, sc, cid, cdist, r0, cnt, lane, part);
     }
 }
 

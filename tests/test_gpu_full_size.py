@@ -12,6 +12,7 @@ import pytest
 import datagen
 import oracle
 from parity import compare
+from stop_model import random_stop_model
 
 pytestmark = pytest.mark.gpu
 
@@ -114,6 +115,72 @@ def test_full_size_fp16_sampled_parity(full):
     ix.close()
 
 
+@pytest.mark.parametrize("L,hop", [(92, 16), (384, 32)])
+def test_full_size_fp16_learned_stop_sampled_parity(full, L, hop):
+    """The timed headline configuration: FP16 storage with the fused learned
+    stop (the learned-stop kernel, autotuned launch, 10,000 queries) at the
+    pool sizes and decision hops the benchmark uses for recall 0.95 (L = 92,
+    hop 16, two 64-entry pool chunks) and 0.99 (L = 384, hop 32, six chunks).
+    With the per-query budgets the kernel reports, the walk equals the
+    oracle's Algorithm 1 over the decoded rows stopped after that many
+    expansions, and the output equals the oracle's FP32 re-rank of that pool
+    (sampled queries); every budget is a grid value at or above the hop."""
+    from paper_1707_00143_amd import learned_stop as ls
+    nsg, X, Q, G, nav, Qd = full["nsg"], full["X"], full["Q"], full["G"], full["nav"], full["Qd"]
+    ix = nsg.load_index(full["Xd"], full["graph"], nav, "f16")
+    k, nq, dev = 10, Q.shape[0], Qd.device
+    P, mean, istd = random_stop_model(nsg, ix, Qd, 21, L=L, hop=hop, center=None)
+    ls.install(ix, P, mean, istd, 1.0, hop=hop)
+    tune, _ = nsg.autotune(ix, Qd, k, L, learned_stop=1)
+    Bu = torch.zeros(nq, dtype=torch.int32, device=dev)
+    ids, dist = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(tune, learned_stop=1, budget=Bu))
+    Bw = torch.zeros(nq, dtype=torch.int32, device=dev)
+    walk_ids, walk_d = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L,
+                                          opts=dict(tune, learned_stop=1, budget=Bw, rerank=-1))
+    Bu, Bw = _np(Bu), _np(Bw)
+    assert (Bu == Bw).all()
+    assert set(Bu.tolist()) <= set(ls.GRID) and Bu.min() >= hop
+    assert len(set(Bu.tolist())) > 3, np.unique(Bu)
+    ids, dist = _np(ids).view(np.uint32), _np(dist)
+    _properties(ids, dist)
+    _, Xt = oracle.quantize("f16", X, oracle.scales("f16", X))
+    o_ids, _, o_hops, _, o_pids, _ = oracle.search(Xt, G, nav, Q[SAMPLE], k, L, pool_stride=L,
+                                                   max_hops=Bu[SAMPLE], threads=16)
+    cut = (o_hops == Bu[SAMPLE]).mean()
+    print(f"L={L} hop={hop}: budgets {np.unique(Bu).tolist()}; {cut * 100:.0f}% of sampled queries stopped "
+          f"by their budget")
+    assert 0.05 < cut < 0.95
+    r = compare(Xt, Q[SAMPLE], _np(walk_ids).view(np.uint32)[SAMPLE], _np(walk_d)[SAMPLE], o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    rr_ids, _ = oracle.rerank(X, Q[SAMPLE], o_pids, k)
+    r = compare(X, Q[SAMPLE], ids[SAMPLE], dist[SAMPLE], rr_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    ix.close()
+
+
+def test_full_size_ground_truth_sampled_exact(full):
+    """The benchmark's ground truth (matrix-core brute force, all 10,000 test
+    queries, k = 100, the launch the benchmark makes) equals the exact kNN
+    definition in FP64 on 160 sampled queries: same id sets up to near-ties
+    at the k-th distance, distances within 1e-5 of FP64; recall counts from
+    nsg_recall_hits equal the plain count of common ids."""
+    nsg, X, Q, Qd = full["nsg"], full["X"], full["Q"], full["Qd"]
+    truth, tdist = nsg.knn_bruteforce(full["Xd"], Qd, 100)
+    s = slice(0, None, 62)
+    ids, dist = _np(truth).view(np.uint32), _np(tdist)
+    o_ids, _ = oracle.knn(X, Q[s], 100)
+    r = compare(X, Q[s], ids[s], dist[s], o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    assert r["exact"] >= 0.99 * r["nq"]
+    # recall counts of a searched result against this truth, as the benchmark forms them
+    ix = nsg.load_index(full["Xd"], full["graph"], full["nav"], "f32")
+    found, _ = nsg.search(ix, Qd, 10, 40)
+    hits = _np(nsg.recall_hits(found.view(-1, 1, 10).contiguous(), truth, 10))[:, 0]
+    want = oracle.recall_at_k(_np(found).view(np.uint32), ids, 10) * 10
+    assert (hits == np.round(want).astype(np.int64)).all()
+    ix.close()
+
+
 def _build(nsg, X, w, dev):
     Xd = torch.from_numpy(X).to(dev)
     knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
@@ -181,7 +248,7 @@ def gist():
                nav=nav)
 
 
-@pytest.mark.parametrize("dt", ["f32", "e4m3"])
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16", "e4m3"])
 def test_precision_workload_sampled_parity(gist, dt):
     """The 960-d precision workload at the size the benchmark reports (GIST-like
     200k x 960, NSG R=70, 1000 queries, L=250): the walk equals the oracle's

@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 from parity import compare
+from stop_model import random_stop_model
 
 pytestmark = pytest.mark.gpu
 
@@ -103,24 +104,6 @@ def test_training_reduces_loss(nsg):
     assert mse < 0.25 * float(np.var(y)), (mse, float(np.var(y)))
 
 
-def _random_model(nsg, ix, Qd, seed):
-    """Random weights on features z-scored with their own statistics (taken
-    from a feature capture of the plain search), output scaled to spread the
-    picks over the grid."""
-    from paper_1707_00143_amd import learned_stop as ls
-    dev = Qd.device
-    feats = torch.empty((Qd.shape[0], nsg.STOP_FEATURES), dtype=torch.float32, device=dev)
-    nsg.search_batched(ix, Qd, k_scalar=10, L_scalar=64, opts=dict(features=feats))
-    mean, istd = nsg.column_stats(feats)
-    P = ls.init_params(nsg.STOP_FEATURES, ls.HIDDEN, seed)
-    Pd = torch.from_numpy(P).to(dev)
-    y = ls.predict(Pd, mean, istd, feats)
-    sd = float(y.std().item()) or 1.0
-    Pd[-(ls.HIDDEN + 1):-1] *= 1.2 / sd          # output spread ~1.2 in log2 L
-    Pd[-1] = (Pd[-1] - float(y.mean().item())) * 1.2 / sd + 5.5
-    return Pd, mean, istd
-
-
 def test_learned_stop_equals_plain_with_chosen_budget(nsg, tiny_index):
     """With the early stop on, each query's output equals the plain search
     stopped after the expansion budget the network picked (on the GPU, and in
@@ -136,7 +119,7 @@ def test_learned_stop_equals_plain_with_chosen_budget(nsg, tiny_index):
     plain = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L)
     hops_plain = torch.zeros(nq, dtype=torch.int64, device=dev)
     nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(hops=hops_plain))
-    P, mean, istd = _random_model(nsg, ix, Qd, 5)
+    P, mean, istd = random_stop_model(nsg, ix, Qd, 5)
     ls.install(ix, P, mean, istd, 1.0)
     Bu = torch.empty(nq, dtype=torch.int32, device=dev)
     feats = torch.empty((nq, nsg.STOP_FEATURES), dtype=torch.float32, device=dev)
@@ -188,6 +171,40 @@ def test_learned_stop_equals_plain_with_chosen_budget(nsg, tiny_index):
     nsg.set_stop_mode(ix, False, 1.0)
     fb = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L)
     assert (fb[0] == plain[0]).all() and (fb[1] == plain[1]).all()
+    ix.close()
+
+
+@pytest.mark.parametrize("dt,L,hop", [("f16", 92, 16), ("bf16", 60, 16), ("e4m3", 60, 16), ("f16", 384, 32),
+                                       ("f32", 300, 32), ("bf16", 200, 32)])
+def test_learned_stop_every_format_and_pool_size(nsg, tiny_index, dt, L, hop):
+    """The fused learned stop in every storage format and pool-chunk count
+    (pools of 2, 4 and 6 register chunks; decision after 16 or 32
+    expansions): with the budgets the kernel reports, the walk equals the
+    oracle's Algorithm 1 over the decoded rows stopped after that many
+    expansions, and the output equals the oracle's FP32 re-rank of that
+    pool (FP32: the walk's own output)."""
+    dev = _dev()
+    from paper_1707_00143_amd import learned_stop as ls
+    X, G, nav, Q = tiny_index["X"], tiny_index["graph"], tiny_index["nav"], tiny_index["Q"]
+    ix = nsg.load_index(torch.from_numpy(X).to(dev), torch.from_numpy(G.view(np.int32)).to(dev), nav, dt)
+    Qd = torch.from_numpy(Q).to(dev)
+    nq, k = len(Q), 10
+    P, mean, istd = random_stop_model(nsg, ix, Qd, 7, L=L, hop=hop, center=None)
+    ls.install(ix, P, mean, istd, 1.0, hop=hop)
+    Bu = torch.zeros(nq, dtype=torch.int32, device=dev)
+    Bw = torch.zeros(nq, dtype=torch.int32, device=dev)
+    ids, dist = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(learned_stop=1, budget=Bu))
+    wi, wd = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(learned_stop=1, budget=Bw, rerank=-1))
+    Bu = _np(Bu)
+    assert (Bu == _np(Bw)).all() and set(Bu.tolist()) <= set(ls.GRID) and Bu.min() >= hop
+    Xt = X if dt == "f32" else oracle.quantize(dt, X, oracle.scales(dt, X))[1]
+    o_ids, _, o_hops, _, o_pids, _ = oracle.search(Xt, G, nav, Q, k, L, pool_stride=L, max_hops=Bu)
+    assert 0 < (o_hops == Bu).sum() < nq              # some searches cut by the budget, some not
+    r = compare(Xt, Q, _np(wi).view(np.uint32), _np(wd), o_ids)
+    assert r["ok"], (dt, L, {a: b for a, b in r.items() if a != "bad"}, r["bad"][:3])
+    rr_ids = o_ids if dt == "f32" else oracle.rerank(X, Q, o_pids, k)[0]
+    r = compare(X, Q, _np(ids).view(np.uint32), _np(dist), rr_ids)
+    assert r["ok"], (dt, L, {a: b for a, b in r.items() if a != "bad"}, r["bad"][:3])
     ix.close()
 
 

@@ -113,6 +113,36 @@ def test_batched_uneven_and_persistent(tiny_gpu, nsg):
             assert r["ok"], (persistent, i, r)
 
 
+def test_out_of_range_per_query_k_and_L_are_clamped_and_counted(tiny_gpu, nsg):
+    """Per-query k[i] / L[i] live on the device and are not checked on the
+    host: values outside [0, out_stride] / [1, L_scalar] are clamped into
+    range (the result equals the search at the clamped values) and each such
+    query is counted in opts.clamped; waves_per_block above 4 is rejected."""
+    t = tiny_gpu
+    dev = t["Qd"].device
+    nq, stride, Lmax = 12, 10, 40
+    k = np.int32([10, 0, -3, 25, 10, 5, 10, 10, 10, 10, 1, 10])
+    L = np.int32([40, 40, 40, 40, 0, -7, 99, 40, 20, 1, 40, 40])
+    kc, Lc = np.clip(k, 0, stride), np.clip(L, 1, Lmax)
+    want = int(((k != kc) | (L != Lc)).sum())
+    cl = torch.zeros(1, dtype=torch.int32, device=dev)
+    ids, dist = nsg.search_batched(t["ix"], t["Qd"][:nq], k=torch.from_numpy(k).to(dev),
+                                   L=torch.from_numpy(L).to(dev), L_scalar=Lmax, out_stride=stride,
+                                   opts=dict(clamped=cl))
+    assert int(cl.item()) == want == 5
+    ids = _np(ids).view(np.uint32)
+    for i in range(nq):
+        if kc[i] == 0:
+            assert (ids[i] == 0xFFFFFFFF).all()      # k = 0 writes nothing (buffer left as filled)
+            continue
+        o_ids, _, _, _ = oracle.search(t["X"], t["graph"], t["nav"], t["Q"][i:i + 1], int(kc[i]), int(Lc[i]))
+        r = compare(t["X"], t["Q"][i:i + 1], ids[i:i + 1, :kc[i]], _np(dist)[i:i + 1, :kc[i]], o_ids)
+        assert r["ok"], (i, r)
+    for bad in (5, 16):
+        with pytest.raises(nsg.NSGError):
+            nsg.search_batched(t["ix"], t["Qd"][:4], k_scalar=10, L_scalar=20, opts=dict(waves_per_block=bad))
+
+
 def test_determinism(tiny_gpu, nsg):
     t = tiny_gpu
     a = nsg.search(t["ix"], t["Qd"], 10, 64)

@@ -159,3 +159,21 @@ def test_per_query_k_and_L(tiny_index):
         assert (ids[i, :k[i]] == one[0]).all() and hops[i] == oh[0]
     # k=100 with L=20: only 20 results, the rest padded
     assert (ids[2, 20:100] == SENT).all() and np.isinf(dist[2, 20:100]).all()
+
+
+def test_counts_distance_evaluations_and_edges_read(tiny_index):
+    """The per-query counts the rooflines credit: distance evaluations =
+    distinct nodes whose distance was computed (the start node plus every
+    first-time neighbour of the expanded nodes), neighbour entries read =
+    the valid row prefixes of the expanded nodes, both rebuilt here from the
+    expansion trace and the graph."""
+    X, G, nav, Q = tiny_index["X"], tiny_index["graph"], tiny_index["nav"], tiny_index["Q"]
+    L, k, nq = 40, 10, 12
+    ne = np.zeros(nq, np.int64)
+    _, _, hops, nd = oracle.search(X, G, nav, Q[:nq], k, L, nedges=ne)
+    for i in range(nq):
+        tr = oracle.search_one(X, G, nav, Q[i], L)["trace"]
+        assert len(tr) == hops[i]
+        rows = [G[v][G[v] != SENT] for v in tr]
+        assert ne[i] == sum(len(r) for r in rows)
+        assert nd[i] == len({int(nav)} | {int(u) for r in rows for u in r})
