@@ -109,6 +109,22 @@ int nsg_search(const nsg_index *idx, const float *queries, int64_t nq,
                int32_t k, int32_t L, uint32_t *out_ids, float *out_dist,
                void *stream);
 
+/*
+ * nsg_search for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * same arguments, result and kernels as nsg_search, and no hipMalloc /
+ * hipFree or other allocating call.  Its scratch memory is the persistent
+ * grid's work counter (batches of 4096 queries or more; one 32-bit word),
+ * held in a 256-byte device array of the library that each GPU keeps until
+ * the process ends; no input size changes what it must hold.  The counter is
+ * cleared by a kernel at the start of every call.  All calls on one GPU
+ * share that array: calls that overlap in time on one GPU (different
+ * streams or threads) race and must not be issued.
+ */
+int nsg_search_noalloc(const nsg_index *idx, const float *queries, int64_t nq,
+                       int32_t k, int32_t L, uint32_t *out_ids, float *out_dist,
+                       void *stream);
+
 /* Options of nsg_search_batched (host struct; zero-initialise, then set). */
 typedef struct nsg_search_opts {
     int32_t persistent;      /* 1: persistent grid with an atomic work counter */

@@ -77,6 +77,7 @@ def _load():
         "nsg_free_index": (None, [P]),
         "nsg_index_info": (i32, [P, P, P, P, P, P]),
         "nsg_search": (i32, [P, P, i64, i32, i32, P, P, P]),
+        "nsg_search_noalloc": (i32, [P, P, i64, i32, i32, P, P, P]),
         "nsg_search_batched": (i32, [P, P, i64, P, P, i32, i32, i32, P, P,
                                      ctypes.POINTER(SearchOpts), P]),
         "nsg_knn_bruteforce": (i32, [P, i64, P, i64, i32, i32, i32, P, P, P]),
@@ -186,6 +187,16 @@ def search(index: Index, queries, k, L, out_ids=None, out_dist=None, stream=None
     if out_dist is None:
         out_dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
     _call("nsg_search", index.handle, _dev(queries, torch.float32, "queries"), nq, int(k), int(L),
+          _dev(out_ids, torch.int32, "out_ids"), _dev(out_dist, torch.float32, "out_dist"), _stream(stream))
+    return out_ids, out_dist
+
+
+def search_noalloc(index: Index, queries, k, L, out_ids, out_dist, stream=None):
+    """nsg_search_noalloc: nsg_search into caller-allocated outputs, with no
+    device allocation by the library (its work counter is a library-held
+    device array shared by every call on the GPU: calls must not overlap)."""
+    nq = queries.shape[0]
+    _call("nsg_search_noalloc", index.handle, _dev(queries, torch.float32, "queries"), nq, int(k), int(L),
           _dev(out_ids, torch.int32, "out_ids"), _dev(out_dist, torch.float32, "out_dist"), _stream(stream))
     return out_ids, out_dist
 
