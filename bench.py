@@ -80,7 +80,9 @@ def main():
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="sift1m_like", choices=["sift1m_like", "deep_uneven", "gist_precision"],
+    ap.add_argument("--shards", type=int, default=8, help="subsets of the partitioned workload")
+    ap.add_argument("--workload", default="sift1m_like",
+                    choices=["sift1m_like", "deep_uneven", "gist_precision", "sift1m_shards"],
                     help="deep_uneven: DEEP-like unit vectors, 100k queries with uneven k and L served in "
                          "batches of 1000 by hipGraph replays of the persistent kernel (a secondary line)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -105,6 +107,8 @@ def main():
         return uneven(args, torch, nsg, datagen, dev)
     if args.workload == "gist_precision":
         return precision(args, torch, nsg, datagen, dev)
+    if args.workload == "sift1m_shards":
+        return sharded(args, torch, nsg, datagen, dev)
     w = datagen.SIFT1M_LIKE if not args.n else datagen.scaled(datagen.SIFT1M_LIKE, args.n)
     k = 10
 
@@ -608,6 +612,99 @@ def gpu_counts(nsg, torch, dev, ix32, ix16, Qd, k, L32, L16, Bu):
                 tot["pool"] += int((pp != -1).sum().item())
             out[key] = tot
     return out
+
+
+def sharded(args, torch, nsg, datagen, dev):
+    """The paper's partitioned scheme on one GPU (one NSG per subset, every
+    query searched in every subset, per-subset top k merged; Sec. 4.2, 4.3):
+    the SIFT-like 1M x 128 set split into `--shards` subsets of consecutive
+    rows, each with its exact 100-NN graph and its own NSG (R=50, l=40,
+    C=500), against one NSG over the whole set.  Reports the index build time
+    of both (the paper notes that building r small graphs costs less than
+    one large one) and the QPS of each at the smallest L reaching recall@10
+    >= the target, FP32 and FP16 storage."""
+    w = datagen.SIFT1M_LIKE if not args.n else datagen.scaled(datagen.SIFT1M_LIKE, args.n)
+    S, k = args.shards, 10
+    X, Q = datagen.base(w), datagen.queries(w)
+    n, nq = X.shape[0], Q.shape[0]
+    Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
+    offs = np.linspace(0, n, S + 1).astype(np.int64)
+    G = torch.empty((n, w.R), dtype=torch.int32, device=dev)
+    navs = []
+    torch.cuda.synchronize()
+    t = time.time()
+    for s in range(S):
+        a, b = int(offs[s]), int(offs[s + 1])
+        xs = Xd[a:b].contiguous()
+        knn, _ = nsg.knn_bruteforce(xs, xs, w.K, exclude_self=True)
+        rs = int(np.random.default_rng(w.seed * 1000 + 101 + s).integers(0, b - a))
+        g, nav, _ = nsg.build(xs, knn, w.Lb, w.C, w.R, rs)
+        G[a:b] = g
+        navs.append(nav)
+        del knn
+    torch.cuda.synchronize()
+    t_shards = time.time() - t
+    log(f"{S} subsets: exact 100-NN graphs + NSG builds in {t_shards:.2f}s")
+    t = time.time()
+    knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
+    graph, nav1, _ = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
+    torch.cuda.synchronize()
+    t_one = time.time() - t
+    del knn
+    log(f"one NSG over all rows: {t_one:.2f}s")
+    truth, _ = nsg.knn_bruteforce(Xd, Qd, 100)
+
+    def recall(ids):
+        return nsg.recall_hits(ids.view(nq, 1, k).contiguous(), truth, k).float().mean().item() / k
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for a_, b_ in ev:
+            a_.record()
+            fn()
+            b_.record()
+        torch.cuda.synchronize()
+        return float(np.mean([a_.elapsed_time(b_) for a_, b_ in ev]))
+
+    grid = list(range(10, 64, 2)) + list(range(64, 160, 4)) + list(range(160, 513, 8))
+    rows = {}
+    for dt in ("f32", "f16"):
+        sh = nsg.load_shards(Xd, offs, G, navs, dt)
+        ix = nsg.load_index(Xd, graph, nav1, dt)
+        for name, fn in (("shards", lambda L: nsg.search_shards(sh, Qd, k, L)), ("single", lambda L: nsg.search(ix, Qd, k, L))):
+            hit = None
+            for L in grid:
+                ids, _ = fn(L)
+                r = recall(ids)
+                if r >= args.target:
+                    hit = (L, r)
+                    break
+            if hit is None:
+                rows[f"{name}_{dt}"] = None
+                continue
+            L = hit[0]
+            out = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), device=dev))
+            f = (lambda: nsg.search_shards(sh, Qd, k, L, out_ids=out[0], out_dist=out[1])) if name == "shards" else \
+                (lambda: nsg.search(ix, Qd, k, L, out_ids=out[0], out_dist=out[1]))
+            ms = timed(f)
+            rows[f"{name}_{dt}"] = dict(L=L, ms=round(ms, 4), qps=round(nq / ms * 1e3, 1), recall10=round(recall(out[0]), 4))
+            log(f"{name} {dt}: {rows[f'{name}_{dt}']}")
+        sh.close()
+        ix.close()
+    head = rows.get("shards_f32")
+    res = {
+        "metric": f"QPS at recall@10>={args.target}, 1M x 128 in {S} subsets (one NSG each, merged top k)",
+        "value": head["qps"] if head else None, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms"] if head else None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w.name}: {n} x {X.shape[1]} in {S} subsets of consecutive rows, NSG R={w.R} "
+                               f"l={w.Lb} C={w.C} per subset from exact {w.K}-NN graphs; {nq} queries; k={k}",
+                   "results": rows, "build_s_subsets": round(t_shards, 2), "build_s_single": round(t_one, 2)},
+    }
+    print(json.dumps(res))
 
 
 def uneven(args, torch, nsg, datagen, dev):

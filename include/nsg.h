@@ -174,6 +174,51 @@ int nsg_search_batched(const nsg_index *idx, const float *queries, int64_t nq,
                        const nsg_search_opts *opts, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Partitioned index (one NSG per subset; Sec. 4.2 "Search On DEEP100M",     */
+/* Sec. 4.3 "Experiments On Taobao Data")                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct nsg_shards nsg_shards;   /* opaque, owned by the library */
+
+/*
+ * Make a partitioned index resident: the point set base[n][d] (FP32) split
+ * into S subsets of consecutive rows, offsets (host, [S + 1]) with
+ * offsets[0] = 0 < offsets[1] < ... < offsets[S] = n, 1 <= S <= 64.  Each
+ * subset has its own NSG: graph[n][R] (device) row i holds the out-neighbours
+ * of point i as ids LOCAL to its subset (0 .. offsets[s+1] - offsets[s] - 1),
+ * sentinel-padded; navs (host, [S]) holds each subset's navigating node as a
+ * local id.  storage / scales as in nsg_load_index (scales computed over the
+ * whole set).  The library keeps one copy of the rows and a graph of global
+ * ids; an entry that is neither a local id of its subset nor the sentinel,
+ * or a navigating node outside its subset, returns NSG_EINVAL.  Synchronous.
+ */
+int nsg_load_shards(const float *base, int64_t n, int32_t d, const int64_t *offsets,
+                    int32_t S, const uint32_t *graph, int32_t R, const uint32_t *navs,
+                    nsg_dtype storage, const float *scales, void *stream,
+                    nsg_shards **out);
+
+/* Release a partitioned index (NULL is a no-op).  Synchronises the device. */
+void nsg_free_shards(nsg_shards *sh);
+
+/* Number of subsets and the underlying index (rows, global-id graph) of a
+ * partitioned index (host outputs; either may be NULL). */
+int nsg_shards_info(const nsg_shards *sh, int32_t *S, nsg_index **index);
+
+/*
+ * Search every query in every subset and merge: Algorithm 1 from each
+ * subset's navigating node with pool size L (one wavefront per (query,
+ * subset) pair, the kernels of nsg_search, re-rank included for reduced
+ * storage), each giving its top k by (distance, id); the result is the k
+ * smallest (distance, id) keys of the union of the S lists (global ids).
+ * out_ids / out_dist [nq][k] (device); padding as in nsg_search.
+ * S * k <= 8192.  The S per-subset lists (nq * S * k * 8 bytes) are
+ * allocated and freed on `stream` (stream-ordered allocations).
+ */
+int nsg_search_shards(const nsg_shards *sh, const float *queries, int64_t nq,
+                      int32_t k, int32_t L, uint32_t *out_ids, float *out_dist,
+                      void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Batches as HIP graphs, and the launch autotuner                           */
 /* ------------------------------------------------------------------------ */
 

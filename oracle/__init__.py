@@ -224,15 +224,17 @@ def merge_topk(ids, dist, k):
     return out_i, out_d
 
 
-def search_sharded(base, offsets, graph, navs, queries, k, L, threads=0):
+def search_sharded(base, offsets, graph, navs, queries, k, L, threads=0, walk_rows=None):
     """The partitioned scheme of the paper's large-scale experiments (one
     sub-NSG per subset, every query searched in every subset, the per-subset
     results merged; Sec. 4.2 "Search On DEEP100M", Sec. 4.3): shard s holds
     base rows offsets[s] .. offsets[s+1] - 1 and its own graph rows (local
     ids, same rows of `graph`) and navigating node navs[s] (local id).
     Algorithm 1 runs in each shard at pool size L; its top k (mapped to
-    global ids) are merged by merge_topk.  Returns (ids, dist, per-shard
-    ids [nq][S][k], per-shard dist)."""
+    global ids) are merged by merge_topk.  With walk_rows (decoded
+    reduced-precision rows [n][d]) each shard's walk runs on them and its
+    final pool is re-ranked on `base` (rerank) before the shard's top k is
+    taken.  Returns (ids, dist, per-shard ids [nq][S][k], per-shard dist)."""
     base, graph, queries = _f32(base), _u32(graph), _f32(queries)
     S = len(offsets) - 1
     nq = queries.shape[0]
@@ -240,7 +242,12 @@ def search_sharded(base, offsets, graph, navs, queries, k, L, threads=0):
     sd = np.full((nq, S, k), np.inf, np.float32)
     for s in range(S):
         a, b = int(offsets[s]), int(offsets[s + 1])
-        ids, dist, _, _ = search(base[a:b], graph[a:b], int(navs[s]), queries, k, L, threads=threads)
+        if walk_rows is None:
+            ids, dist, _, _ = search(base[a:b], graph[a:b], int(navs[s]), queries, k, L, threads=threads)
+        else:
+            _, _, _, _, pids, _ = search(_f32(walk_rows)[a:b], graph[a:b], int(navs[s]), queries, k, L,
+                                         pool_stride=L, threads=threads)
+            ids, dist = rerank(base[a:b], queries, pids, k)
         ok = ids != SENT
         sid[:, s] = np.where(ok, ids + np.uint32(a), SENT)
         sd[:, s] = dist

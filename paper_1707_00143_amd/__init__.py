@@ -89,6 +89,10 @@ def _load():
         "nsg_mlp_forward": (i32, [P, i32, i32, P, i64, P, P]),
         "nsg_recall_hits": (i32, [P, i64, i32, i32, P, i32, P, P]),
         "nsg_column_stats": (i32, [P, i64, i32, P, P, P]),
+        "nsg_load_shards": (i32, [P, i64, i32, P, i32, P, i32, P, i32, P, P, ctypes.POINTER(P)]),
+        "nsg_free_shards": (None, [P]),
+        "nsg_shards_info": (i32, [P, P, P]),
+        "nsg_search_shards": (i32, [P, P, i64, i32, i32, P, P, P]),
         "nsg_search_graph_create": (i32, [P, P, i64, P, P, i32, i32, i32, P, P, ctypes.POINTER(SearchOpts),
                                           ctypes.POINTER(P)]),
         "nsg_search_graph_launch": (i32, [P, P]),
@@ -220,6 +224,68 @@ def search_batched(index: Index, queries, k=None, L=None, k_scalar=10, L_scalar=
           _dev(k, torch.int32, "k"), _dev(L, torch.int32, "L"), int(k_scalar), int(L_scalar), int(out_stride),
           _dev(out_ids, torch.int32, "out_ids"), _dev(out_dist, torch.float32, "out_dist"), ctypes.byref(o),
           _stream(stream))
+    return out_ids, out_dist
+
+
+class Shards:
+    """A resident partitioned index (nsg_load_shards): S subsets of consecutive
+    rows, one NSG each.  `index` is the underlying single index (rows and the
+    graph in global ids), usable with every search entry point of one graph."""
+
+    def __init__(self, handle, offsets, storage):
+        self._h = handle
+        self.offsets = list(offsets)
+        self.S = len(self.offsets) - 1
+        self.storage = storage
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("partitioned index is closed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            _load().nsg_free_shards(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def load_shards(base, offsets, graph, navs, storage="f32", scales=None, stream=None) -> Shards:
+    """nsg_load_shards: base [n][d] float32, offsets (S + 1 ints, host), graph
+    [n][R] int32 holding each subset's LOCAL ids, navs (S local ids, host)."""
+    n, d = base.shape
+    R = graph.shape[1]
+    offs = (ctypes.c_int64 * len(offsets))(*[int(o) for o in offsets])
+    S = len(offsets) - 1
+    nv = (ctypes.c_uint32 * S)(*[int(v) for v in navs])
+    st = DTYPES[storage] if isinstance(storage, str) else int(storage)
+    h = ctypes.c_void_p()
+    _call("nsg_load_shards", _dev(base, torch.float32, "base"), n, d, offs, S, _dev(graph, torch.int32, "graph"), R,
+          nv, st, _dev(scales, torch.float32, "scales"), _stream(stream), ctypes.byref(h))
+    return Shards(h, offsets, st)
+
+
+def search_shards(shards: Shards, queries, k, L, out_ids=None, out_dist=None, stream=None):
+    """nsg_search_shards: every query in every subset, merged top k (global ids)."""
+    nq = queries.shape[0]
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+    if out_dist is None:
+        out_dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    _call("nsg_search_shards", shards.handle, _dev(queries, torch.float32, "queries"), nq, int(k), int(L),
+          _dev(out_ids, torch.int32, "out_ids"), _dev(out_dist, torch.float32, "out_dist"), _stream(stream))
     return out_ids, out_dist
 
 

@@ -59,3 +59,15 @@ def test_exhaustive_pools_in_every_shard_give_exact_knn():
     for s in range(3):
         v = sid[:, s][sid[:, s] != SENT].astype(np.int64)
         assert ((v >= offs[s]) & (v < offs[s + 1])).all()
+
+
+def test_rerank_walk_over_exact_rows_changes_nothing():
+    """Walking decoded rows that equal the FP32 rows, then re-ranking the pool
+    in FP32, is the plain partitioned search (the re-rank of a pool sorted
+    by the same distances keeps its first k)."""
+    w = datagen.scaled(datagen.TINY, 1200, 12)
+    X, Q = datagen.base(w), datagen.queries(w)
+    offs, G, navs = _shards(X, 2)
+    a, ad, _, _ = oracle.search_sharded(X, offs, G, navs, Q, 10, 30)
+    b, bd, _, _ = oracle.search_sharded(X, offs, G, navs, Q, 10, 30, walk_rows=X.copy())
+    assert (a == b).all() and (ad == bd).all()
