@@ -39,12 +39,15 @@ T0 = time.time()
 
 
 def source_sha256():
-    """Hash of the library sources (kernels, host code, ABI header)."""
+    """Hash of the sources the search kernels are built from (kernel
+    templates, their instantiations, the launch code, index residency and
+    the ABI header)."""
     import glob
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1707_00143_amd", "csrc")
-    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")))
+    files = sorted(glob.glob(os.path.join(csrc, "search*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")) +
+                   [os.path.join(csrc, "api.hip")])
     for f in files + [os.path.join(ROOT, "include", "nsg.h")]:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -82,11 +85,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--shards", type=int, default=8, help="subsets of the partitioned workload")
     ap.add_argument("--workload", default="sift1m_like",
-                    choices=["sift1m_like", "deep_uneven", "gist_precision", "sift1m_shards"],
+                    choices=["sift1m_like", "deep_uneven", "gist_precision", "sift1m_shards", "sift1m_ablation"],
                     help="deep_uneven: DEEP-like unit vectors, 100k queries with uneven k and L served in "
                          "batches of 1000 by hipGraph replays of the persistent kernel (a secondary line)")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="after the timed region, copy a 1 GiB buffer twice (scales HBM byte counters)")
+                    help="after the timed region, stream a 1 GiB buffer twice through an elementwise kernel "
+                         "(scales HBM byte counters)")
     ap.add_argument("--cache", default="", help="directory: reuse (or save) the graph, L and model of a "
                                                  "previous run of the same workload (profiling passes)")
     ap.add_argument("--only-target", action="store_true",
@@ -96,6 +100,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
+    # progress lines of the index builds on stderr (the JSON line is on stdout)
+    os.environ.setdefault("NSG_LOG", "1")
     import torch
 
     import datagen
@@ -109,6 +115,8 @@ def main():
         return precision(args, torch, nsg, datagen, dev)
     if args.workload == "sift1m_shards":
         return sharded(args, torch, nsg, datagen, dev)
+    if args.workload == "sift1m_ablation":
+        return ablation(args, torch, nsg, datagen, dev)
     w = datagen.SIFT1M_LIKE if not args.n else datagen.scaled(datagen.SIFT1M_LIKE, args.n)
     k = 10
 
@@ -482,12 +490,14 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
     log(f"roofline plain FP32: {roof32}")
 
     if args.calib_copy:
+        # a plain streaming kernel of known size for the HBM byte counters:
+        # an elementwise negation reads 1 GiB and writes 1 GiB (twice)
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(2):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
-        log("calibration copy: 2 x 1 GiB read + 1 GiB written")
+        log("calibration kernel: 2 x (1 GiB read + 1 GiB written)")
 
     f16row = head.get("plain_fp16")
     res = {
@@ -707,6 +717,104 @@ def sharded(args, torch, nsg, datagen, dev):
     print(json.dumps(res))
 
 
+def ablation(args, torch, nsg, datagen, dev):
+    """The comparisons behind the paper's design choices (Sec. 4.1.2, 4.3,
+    5): on the SIFT-like 1M x 128 set, the NSG searched from its navigating
+    node, the same NSG searched from one random node per query, and NSG-Naive
+    (MRNG selection over each node's kNN list only: no navigating node, no
+    connectivity repair) searched from L random nodes per query (random
+    initialization).  For each, the smallest L reaching recall@10 >= the
+    target, its QPS (FP32 storage) and its mean expansions and distance
+    evaluations per query.  Random nodes are drawn on the host, seeded."""
+    w = datagen.SIFT1M_LIKE if not args.n else datagen.scaled(datagen.SIFT1M_LIKE, args.n)
+    k = 10
+    X, Q = datagen.base(w), datagen.queries(w)
+    n, nq = X.shape[0], Q.shape[0]
+    Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
+    knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
+    torch.cuda.synchronize()
+    t = time.time()
+    graph, nav, _ = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
+    torch.cuda.synchronize()
+    t_nsg = time.time() - t
+    log(f"NSG build {t_nsg:.2f}s")
+    t = time.time()
+    naive = nsg.build_naive(Xd, knn, w.R)
+    torch.cuda.synchronize()
+    t_naive = time.time() - t
+    del knn
+    log(f"NSG-Naive build {t_naive:.2f}s")
+    truth, _ = nsg.knn_bruteforce(Xd, Qd, k)
+    rng = np.random.default_rng(w.seed * 1000 + 211)
+    init_all = torch.from_numpy(rng.integers(0, n, size=(nq, 512)).astype(np.int32)).to(dev)
+
+    def recall(ids):
+        return nsg.recall_hits(ids.view(nq, 1, k).contiguous(), truth, k).float().mean().item() / k
+
+    def deg(g):
+        dg = (g != -1).sum(1).float()
+        return round(dg.mean().item(), 2), int(dg.max().item())
+
+    variants = (("nsg_navigating_node", graph, nav, 0), ("nsg_random_start", graph, nav, 1),
+                ("nsg_naive_random_init", naive, 0, -1))
+    grid = list(range(10, 64, 2)) + list(range(64, 160, 4)) + list(range(160, 513, 8))
+    rows = {}
+    for name, g, start, m in variants:
+        ix = nsg.load_index(Xd, g, start, "f32")
+
+        def opts_for(L, extra=None):
+            mm = L if m < 0 else m
+            o = {} if mm == 0 else dict(init_ids=init_all[:, :mm].contiguous(), init_n=mm)
+            o.update(extra or {})
+            return o
+
+        hit, last = None, None
+        for L in grid:
+            ids, _ = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=opts_for(L))
+            last = (L, recall(ids))
+            if last[1] >= args.target:
+                hit = last
+                break
+        if hit is None:
+            rows[name] = dict(reached=False, best_L=last[0], recall10=round(last[1], 4))
+            log(f"{name}: recall@10 {last[1]:.4f} at L={last[0]} (target not reached)")
+            ix.close()
+            continue
+        L = hit[0]
+        o = opts_for(L)
+        out = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), device=dev))
+        for _ in range(args.warmup):
+            nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, out_ids=out[0], out_dist=out[1], opts=o)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for a_, b_ in ev:
+            a_.record()
+            nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, out_ids=out[0], out_dist=out[1], opts=o)
+            b_.record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in ev]))
+        hops = torch.zeros(nq, dtype=torch.int64, device=dev)
+        nd = torch.zeros(nq, dtype=torch.int64, device=dev)
+        nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=opts_for(L, dict(hops=hops, ndist=nd)))
+        aod, mod = deg(g)
+        rows[name] = dict(reached=True, L=L, recall10=round(recall(out[0]), 4), ms=round(ms, 4),
+                          qps=round(nq / ms * 1e3, 1), expansions=round(hops.double().mean().item(), 2),
+                          distance_evals=round(nd.double().mean().item(), 1), AOD=aod, MOD=mod)
+        log(f"{name}: {rows[name]}")
+        ix.close()
+    head = rows["nsg_navigating_node"]
+    res = {
+        "metric": f"QPS at recall@10>={args.target}: NSG from its navigating node vs a random start vs NSG-Naive",
+        "value": head.get("qps"), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head.get("ms"), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w.name}: {n} x {X.shape[1]}, {nq} queries, k={k}; NSG R={w.R} l={w.Lb} C={w.C} "
+                               f"and NSG-Naive R={w.R}, both from the exact {w.K}-NN graph",
+                   "results": rows, "build_s_nsg": round(t_nsg, 2), "build_s_naive": round(t_naive, 2)},
+    }
+    print(json.dumps(res))
+
+
 def uneven(args, torch, nsg, datagen, dev):
     """DEEP-like unit vectors (2000-component mixture, d=96), NSG R=32; a
     stream of 100k queries with k uniform in {1,10,100} and L uniform in
@@ -720,6 +828,8 @@ def uneven(args, torch, nsg, datagen, dev):
     Qd = torch.from_numpy(Q).to(dev)
     t = time.time()
     knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
+    torch.cuda.synchronize()
+    log(f"{w.name}: exact {w.K}-NN graph {time.time() - t:.1f}s")
     graph, nav, rep = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
     torch.cuda.synchronize()
     t_idx = time.time() - t
@@ -802,12 +912,13 @@ def precision(args, torch, nsg, datagen, dev):
     knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
     torch.cuda.synchronize()
     t_knn = time.time() - t
+    log(f"{w.name}: exact {w.K}-NN graph {t_knn:.1f}s")
     t = time.time()
     graph, nav, rep = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
     torch.cuda.synchronize()
     t_build = time.time() - t
     del knn
-    log(f"{w.name}: knn graph {t_knn:.1f}s, build {t_build:.1f}s, repair edges {rep}")
+    log(f"{w.name}: build {t_build:.1f}s, repair edges {rep}")
     truth, _ = nsg.knn_bruteforce(Xd, Qd, k)
     tr = truth.cpu().numpy().view(np.uint32)
     nq = Q.shape[0]

@@ -152,6 +152,12 @@ typedef struct nsg_search_opts {
     int32_t *clamped;        /* device int32 counter (caller-initialised), or NULL: incremented
                                 once for every query whose k[i] lies outside [0, out_stride] or
                                 whose L[i] lies outside [1, L_scalar] (see below) */
+    const uint32_t *init_ids; /* device [nq][init_n] node ids, or NULL: query i's initial pool is
+                                the set of these nodes (each visited once, the L nearest kept)
+                                instead of the navigating node -- random initialization (the
+                                search of the NSG-Naive baseline, Sec. 4.1.2) or random starts
+                                (Sec. 4.1.3); ids >= n are ignored */
+    int32_t init_n;          /* 0 .. 512; 0: start at the navigating node */
 } nsg_search_opts;
 
 /*
@@ -284,11 +290,24 @@ int nsg_knn_bruteforce(const float *base, int64_t n, const float *queries,
  * edges; then DFS-tree connectivity repair from the navigating node.
  * graph_out [n][R] (device), *nav_out (host).  *repair_edges (host, may be
  * NULL) receives the number of edges the repair added.  Synchronous.
+ * With the environment variable NSG_LOG set (non-empty, not "0") it writes
+ * one progress line per phase to stderr.
  */
 int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t *knn,
               int32_t K, int32_t Lb, int32_t C, int32_t R, uint32_t rand_start,
               uint32_t *graph_out, uint32_t *nav_out, int64_t *repair_edges,
               void *stream);
+
+/*
+ * NSG-Naive, the baseline of Sec. 4.1.2: the MRNG edge selection of Algorithm
+ * 2 applied to each node's own kNN list only (candidates = the K neighbours
+ * of knn[n][K], sorted by (distance, id)), at most R edges per node; no
+ * navigating node, no search-collect, no connectivity repair.  Searches on it
+ * start from random nodes (nsg_search_opts.init_ids).  graph_out [n][R]
+ * (device, sentinel padded).  Synchronous.
+ */
+int nsg_build_naive(const float *base, int64_t n, int32_t d, const uint32_t *knn,
+                    int32_t K, int32_t R, uint32_t *graph_out, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Learned early termination (an extension; not in the paper)                */

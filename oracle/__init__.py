@@ -26,6 +26,12 @@ Parity status per function (see the tests named):
   search_sharded  pinned: one shard = the plain search; exhaustive pools in
   / merge_topk    every shard = exact kNN of the whole base; hand merge
                   with ties and padding (test_oracle_shards)
+  build_naive     pinned: with every other node as candidates and no degree
+                  cap it is the naive MRNG; rows are subsets of the kNN rows
+                  obeying the pairwise rule (test_oracle_ablations)
+  search init_ids pinned: a set holding every node = exhaustive pool (exact
+                  kNN); a one-node set = the search started there
+                  (test_oracle_ablations)
   rerank          pinned: hand case with a tie and padding; a pool holding
                   the exact top-k returns it (integer data, exact distances);
                   per-query stride (test_oracle_rerank)
@@ -69,7 +75,8 @@ def _get():
             "oracle_l2sq_f64": (f64, [P, P, i32]),
             "oracle_knn": (i32, [P, i64, i32, P, i64, i32, i32, i32, P, P]),
             "oracle_search_batch": (i32, [P, i64, i32, P, i32, u32, P, i64, i32, i32, P, P,
-                                          i32, P, P, P, P, P, P, i32, P, P, i32]),
+                                          i32, P, P, P, P, P, P, i32, P, P, P, i32, i32]),
+            "oracle_build_naive": (i32, [P, i64, i32, P, i32, i32, P]),
             "oracle_search_one": (i32, [P, i64, i32, P, i32, u32, P, i32, i64, P, P, P,
                                         P, i64, P, P, i64, P]),
             "oracle_centroid": (i32, [P, i64, i32, P]),
@@ -145,12 +152,14 @@ def knn_graph(base, K):
 # --------------------------------------------------------------------------
 
 def search(base, graph, start, queries, k, L, k_arr=None, L_arr=None, pool_stride=0,
-           max_hops=None, threads=0, nedges=None):
+           max_hops=None, threads=0, nedges=None, init_ids=None):
     """Batched Algorithm 1 from `start`.  Returns (ids, dist, hops, ndist[, pool_ids,
     pool_dist]).  With per-query k_arr / L_arr the outputs are [nq][max k].
     max_hops: optional per-query expansion budget (<= 0: none).  nedges: an
     optional int64 [nq] array that receives the neighbour entries each query
-    read (the valid row prefixes of its expanded nodes)."""
+    read (the valid row prefixes of its expanded nodes).  init_ids: optional
+    [nq][m] node ids; each query's initial pool is that set (random
+    initialization) instead of {start}."""
     base, graph, queries = _f32(base), _u32(graph), _f32(queries)
     n, d = base.shape
     R = graph.shape[1]
@@ -167,6 +176,11 @@ def search(base, graph, start, queries, k, L, k_arr=None, L_arr=None, pool_strid
         pids = np.empty((nq, pool_stride), np.uint32)
         pd = np.empty((nq, pool_stride), np.float32)
     mh = None if max_hops is None else np.ascontiguousarray(np.broadcast_to(max_hops, (nq,)), np.int32)
+    ini, ini_n = None, 0
+    if init_ids is not None:
+        ini = np.ascontiguousarray(init_ids, np.uint32)
+        assert ini.ndim == 2 and ini.shape[0] == nq
+        ini_n = ini.shape[1]
     ne = None
     if nedges is not None:
         assert nedges.dtype == np.int64 and nedges.shape == (nq,) and nedges.flags.c_contiguous
@@ -174,7 +188,7 @@ def search(base, graph, start, queries, k, L, k_arr=None, L_arr=None, pool_strid
     _check(_get().oracle_search_batch(
         _p(base), n, d, _p(graph), R, int(start), _p(queries), nq, int(k), int(L),
         _p(k_arr_c), _p(L_arr_c), kst, _p(ids), _p(dist), _p(hops), _p(nd),
-        _p(pids), _p(pd), int(pool_stride), _p(mh), _p(ne), int(threads)), "search")
+        _p(pids), _p(pd), int(pool_stride), _p(mh), _p(ne), _p(ini), ini_n, int(threads)), "search")
     if pool_stride:
         return ids, dist, hops, nd, pids, pd
     return ids, dist, hops, nd
@@ -303,6 +317,17 @@ def build_nsg(base, knn_g, Lb, C, m, rand_start, threads=0):
                                    int(m), int(rand_start), _p(g), _p(nav), _p(stats),
                                    int(threads)), "build_nsg")
     return g, int(nav[0]), int(stats[0])
+
+
+def build_naive(base, knn_g, m):
+    """NSG-Naive (Sec. 4.1.2): MRNG edge selection on each node's kNN list
+    only, at most m edges, no navigating node, no repair.  Returns [n][m]
+    uint32, sentinel padded."""
+    base, knn_g = _f32(base), _u32(knn_g)
+    n, d = base.shape
+    g = np.empty((n, m), np.uint32)
+    _check(_get().oracle_build_naive(_p(base), n, d, _p(knn_g), knn_g.shape[1], int(m), _p(g)), "build_naive")
+    return g
 
 
 def mrng_naive(base, prec=64):

@@ -221,7 +221,8 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
                        uint32_t start, const float *q, int L, ws_t *w,
                        int64_t *hops_out, int64_t *ndist_out, int64_t *nedges_out,
                        int keep_visited, int64_t stop_hop,
-                       uint32_t *trace, int64_t trace_cap)
+                       uint32_t *trace, int64_t trace_cap,
+                       const uint32_t *init, int init_n)
 {
     int64_t hops = 0, ndist = 0, nedges = 0;
     w->cur++;
@@ -230,15 +231,26 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
         w->cur = 1;
     }
     w->vis_cnt = 0;
-    ws_pool_reserve(w, L + R);
+    ws_pool_reserve(w, (L > init_n ? L : init_n) + R);
     pent_t *pool = w->pool;
-    int size = 1;
-    pool[0].dist = oracle_l2sq_f32(q, base + (int64_t)start * d, d);
-    pool[0].id = start;
-    pool[0].checked = 0;
-    w->stamp[start] = w->cur;
-    ndist++;
-    if (keep_visited) ws_vis_push(w, pool[0].dist, start);
+    int size = 0;
+    /* S.add(p): the start node, or (random initialization) every distinct
+     * node of `init`, sorted and cut to L */
+    const uint32_t *ini = init_n > 0 ? init : &start;
+    const int nini = init_n > 0 ? init_n : 1;
+    for (int j = 0; j < nini; ++j) {
+        uint32_t u = ini[j];
+        if (u >= (uint64_t)w->n || w->stamp[u] == w->cur) continue;
+        w->stamp[u] = w->cur;
+        pool[size].dist = oracle_l2sq_f32(q, base + (int64_t)u * d, d);
+        pool[size].id = u;
+        pool[size].checked = 0;
+        ndist++;
+        if (keep_visited) ws_vis_push(w, pool[size].dist, u);
+        size++;
+    }
+    qsort(pool, (size_t)size, sizeof(pent_t), pent_cmp);
+    if (size > L) size = L;
 
     for (;;) {
         if (stop_hop >= 0 && hops >= stop_hop) break;
@@ -286,6 +298,10 @@ static int search_core(const float *base, int d, const uint32_t *graph, int R,
  * stop); a query stops after that many expansions; values <= 0: no budget.
  * nedges (optional): per query, the neighbour entries read (valid row
  * prefixes of the expanded nodes, visited or not).
+ * init_ids (optional, [nq][init_n]): the initial pool of each query is the
+ * set of these nodes instead of {start} (random initialization, the search
+ * of the NSG-Naive baseline, Sec. 4.1.2; random starts, Sec. 4.1.3).
+ * Growing the pool to hold them: the pool holds max(L, init_n) + R entries.
  * threads <= 0 uses the OpenMP default.
  */
 int oracle_search_batch(const float *base, int64_t n, int d,
@@ -295,11 +311,13 @@ int oracle_search_batch(const float *base, int64_t n, int d,
                         int k_stride, uint32_t *out_ids, float *out_dist,
                         int64_t *hops, int64_t *ndist,
                         uint32_t *pool_ids, float *pool_dist, int pool_stride,
-                        const int32_t *max_hops_arr, int64_t *nedges, int threads)
+                        const int32_t *max_hops_arr, int64_t *nedges,
+                        const uint32_t *init_ids, int init_n, int threads)
 {
     if (n < 1 || d < 1 || R < 1 || start >= (uint64_t)n || nq < 0) return -1;
     int maxL = L;
     if (L_arr) { maxL = 1; for (int64_t i = 0; i < nq; ++i) if (L_arr[i] > maxL) maxL = L_arr[i]; }
+    if (init_ids && init_n > maxL) maxL = init_n;
     int bad = 0;
     int nth = threads > 0 ? threads : omp_get_max_threads();
 #pragma omp parallel num_threads(nth)
@@ -314,7 +332,8 @@ int oracle_search_batch(const float *base, int64_t n, int d,
             int64_t budget = (max_hops_arr && max_hops_arr[qi] > 0) ? max_hops_arr[qi] : -1;
             int64_t h = 0, nd = 0, ne = 0;
             int size = search_core(base, d, graph, R, start, queries + qi * (int64_t)d,
-                                   LL, &w, &h, &nd, &ne, 0, budget, NULL, 0);
+                                   LL, &w, &h, &nd, &ne, 0, budget, NULL, 0,
+                                   init_ids ? init_ids + qi * (int64_t)init_n : NULL, init_ids ? init_n : 0);
             for (int j = 0; j < kk; ++j) {
                 out_ids[qi * k_stride + j] = j < size ? w.pool[j].id : SENT;
                 out_dist[qi * k_stride + j] = j < size ? w.pool[j].dist : INFINITY;
@@ -352,7 +371,7 @@ int oracle_search_one(const float *base, int64_t n, int d,
     if (ws_init(&w, n, L + R) != 0) { ws_free(&w); return -2; }
     int64_t h = 0, nd = 0;
     int size = search_core(base, d, graph, R, start, q, L, &w, &h, &nd, NULL, 1,
-                           stop_hop, trace, trace_cap);
+                           stop_hop, trace, trace_cap, NULL, 0);
     for (int j = 0; j < size; ++j) {
         if (pool_ids) pool_ids[j] = w.pool[j].id;
         if (pool_dist) pool_dist[j] = w.pool[j].dist;
@@ -398,7 +417,7 @@ int oracle_navigating_node(const float *base, int64_t n, int d,
     oracle_centroid(base, n, d, c);
     ws_t w;
     if (ws_init(&w, n, Lb + K) != 0) { ws_free(&w); free(c); return -2; }
-    search_core(base, d, knn, K, rand_start, c, Lb, &w, NULL, NULL, NULL, 0, -1, NULL, 0);
+    search_core(base, d, knn, K, rand_start, c, Lb, &w, NULL, NULL, NULL, 0, -1, NULL, 0, NULL, 0);
     *nav = w.pool[0].id;
     ws_free(&w);
     free(c);
@@ -450,7 +469,7 @@ static int collect_select(const float *base, int64_t n, int d,
                           int C, int m, uint32_t v, ws_t *w, uint32_t *row)
 {
     const float *qv = base + (int64_t)v * d;
-    search_core(base, d, knn, K, nav, qv, Lb, w, NULL, NULL, NULL, 1, -1, NULL, 0);
+    search_core(base, d, knn, K, nav, qv, Lb, w, NULL, NULL, NULL, 1, -1, NULL, 0, NULL, 0);
     /* the visited stamp marks exactly the visited ids; add unvisited kNN ids */
     for (int j = 0; j < K; ++j) {
         uint32_t u = knn[(int64_t)v * K + j];
@@ -468,6 +487,47 @@ static int collect_select(const float *base, int64_t n, int d,
     int cnt = mrng_select(base, d, w->vis, ne, m, row);
     for (int j = cnt; j < m; ++j) row[j] = SENT;
     return cnt;
+}
+
+/*
+ * NSG-Naive (the baseline of Sec. 4.1.2): the MRNG edge selection applied to
+ * each node's own kNN list only — candidates = the K kNN neighbours of v
+ * (self and sentinels skipped), sorted by (distance to v, id) — with at most
+ * m edges; no navigating node, no search-collect, no connectivity repair.
+ * graph_out [n][m] sentinel padded.
+ */
+int oracle_build_naive(const float *base, int64_t n, int d, const uint32_t *knn, int K, int m,
+                       uint32_t *graph_out)
+{
+    if (n < 1 || d < 1 || K < 1 || m < 1) return -1;
+    int bad = 0;
+#pragma omp parallel
+    {
+        pent_t *E = (pent_t *)malloc(sizeof(pent_t) * (size_t)K);
+        if (!E) bad = 1;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t v = 0; v < n; ++v) {
+            if (!E) continue;
+            int ne = 0;
+            for (int j = 0; j < K; ++j) {
+                uint32_t u = knn[v * K + j];
+                if (u == SENT || u >= (uint64_t)n || u == (uint32_t)v) continue;
+                int dup = 0;
+                for (int t = 0; t < ne; ++t) dup |= E[t].id == u;
+                if (dup) continue;
+                E[ne].id = u;
+                E[ne].dist = oracle_l2sq_f32(base + v * d, base + (int64_t)u * d, d);
+                E[ne].checked = 0;
+                ne++;
+            }
+            qsort(E, (size_t)ne, sizeof(pent_t), pent_cmp);
+            uint32_t *row = graph_out + v * m;
+            int cnt = mrng_select(base, d, E, ne, m, row);
+            for (int j = cnt; j < m; ++j) row[j] = SENT;
+        }
+        free(E);
+    }
+    return bad ? -2 : 0;
 }
 
 /* Exposed per-node step for tests. */
@@ -538,7 +598,7 @@ int oracle_repair(const float *base, int64_t n, int d, uint32_t *graph, int m,
         uint32_t u = (uint32_t)scan;
         const float *qu = base + (int64_t)u * d;
         int size = search_core(base, d, graph, m, nav, qu, Lb, &w, NULL, NULL, NULL, 0,
-                               -1, NULL, 0);
+                               -1, NULL, 0, NULL, 0);
         int64_t wsel = -1;
         for (int t = 0; t < size; ++t) {
             uint32_t c = w.pool[t].id;

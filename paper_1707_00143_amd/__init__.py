@@ -56,6 +56,8 @@ class SearchOpts(ctypes.Structure):
         ("counter", ctypes.c_void_p),
         ("max_hops", ctypes.c_int32),
         ("clamped", ctypes.c_void_p),
+        ("init_ids", ctypes.c_void_p),
+        ("init_n", ctypes.c_int32),
     ]
 
 
@@ -82,6 +84,7 @@ def _load():
                                      ctypes.POINTER(SearchOpts), P]),
         "nsg_knn_bruteforce": (i32, [P, i64, P, i64, i32, i32, i32, P, P, P]),
         "nsg_build": (i32, [P, i64, i32, P, i32, i32, i32, i32, u32, P, P, P, P]),
+        "nsg_build_naive": (i32, [P, i64, i32, P, i32, i32, P, P]),
         "nsg_load_stop_model": (i32, [P, P, ctypes.c_size_t, i32, i32, i32, i32]),
         "nsg_set_stop_mode": (i32, [P, i32, f32]),
         "nsg_mlp_forward_backward": (i32, [P, i32, i32, P, P, i64, P, P, P, P]),
@@ -312,6 +315,16 @@ def build(base, knn, Lb, C, R, rand_start, stream=None):
           int(C), int(R), int(rand_start), _dev(g, torch.int32, "graph"), ctypes.byref(nav), ctypes.byref(rep),
           _stream(stream))
     return g, int(nav.value), int(rep.value)
+
+
+def build_naive(base, knn, R, stream=None):
+    """nsg_build_naive (the NSG-Naive baseline): returns graph int32 [n][R]."""
+    n, d = base.shape
+    K = knn.shape[1]
+    g = torch.empty((n, R), dtype=torch.int32, device=base.device)
+    _call("nsg_build_naive", _dev(base, torch.float32, "base"), n, d, _dev(knn, torch.int32, "knn"), K, int(R),
+          _dev(g, torch.int32, "graph"), _stream(stream))
+    return g
 
 
 def load_stop_model(index: Index, blob: bytes, n_in: int, h: int, hop: int, grid_n: int):

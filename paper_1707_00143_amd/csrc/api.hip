@@ -329,6 +329,8 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
         o.lanes_per_row != 64)
         return fail(NSG_EINVAL, "lanes_per_row must be 0, 8, 16, 32 or 64");
     if (o.blocks < 0) return fail(NSG_EINVAL, "blocks < 0");
+    if (o.init_n < 0 || o.init_n > kMaxL) return fail(NSG_EINVAL, "init_n=%d out of range [0, %d]", o.init_n, kMaxL);
+    if (o.init_n > 0 && !o.init_ids) return fail(NSG_EINVAL, "init_n > 0 needs init_ids");
     if (nq == 0) return NSG_OK;
     SearchArgs a{};
     a.idx = idx;
@@ -358,6 +360,8 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.lanes_per_row = o.lanes_per_row;
     a.counter = o.counter;
     a.clamped = o.clamped;
+    a.init_ids = o.init_ids;
+    a.init_n = o.init_n;
     a.pool_ids = o.pool_ids;
     a.pool_dist = o.pool_dist;
     a.pool_stride = o.pool_stride;

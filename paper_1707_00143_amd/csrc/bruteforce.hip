@@ -50,11 +50,21 @@ __device__ inline void bsync() { __syncthreads(); }
 // column; mean_finish_kernel adds the partials in block order, so the result
 // is deterministic and close to the correctly rounded mean.
 __global__ void colsum_part_kernel(const float *x, int64_t n, int d, float2 *part) {
+    const int64_t G = gridDim.x;
     for (int j0 = 0; j0 < d; j0 += blockDim.x) {
         const int j = j0 + threadIdx.x;
         if (j >= d) continue;
         float s = 0.0f, c = 0.0f;
-        for (int64_t i = blockIdx.x; i < n; i += gridDim.x) neumaier_add(s, c, x[i * d + j]);
+        int64_t i = blockIdx.x;
+        for (; i + 3 * G < n; i += 4 * G) {   // four independent loads in flight, added in row order
+            const float v0 = x[i * d + j], v1 = x[(i + G) * d + j];
+            const float v2 = x[(i + 2 * G) * d + j], v3 = x[(i + 3 * G) * d + j];
+            neumaier_add(s, c, v0);
+            neumaier_add(s, c, v1);
+            neumaier_add(s, c, v2);
+            neumaier_add(s, c, v3);
+        }
+        for (; i < n; i += G) neumaier_add(s, c, x[i * d + j]);
         part[(size_t)blockIdx.x * d + j] = make_float2(s, c);
     }
 }
@@ -298,7 +308,7 @@ __global__ void __launch_bounds__(256) bf_rerank_kernel(const float *base, const
     }
 }
 
-int mean_blocks(int64_t n) { return (int)std::min<int64_t>(n, 256); }
+int mean_blocks(int64_t n) { return (int)std::min<int64_t>(n, 1024); }
 
 int launch_mean(const float *x, int64_t n, int d, float *mu, float2 *part, hipStream_t st) {
     const int nblk = mean_blocks(n);

@@ -119,6 +119,10 @@ struct SearchArgs {
     // i / shards in shard i % shards from shard_starts[i % shards] (device)
     int32_t shards;           // 0 or 1: one graph
     const uint32_t *shard_starts;
+    const uint32_t *init_ids; // [nq][init_n] initial pool node sets (device), or NULL
+    int32_t init_n;
+    uint32_t *trace_ids;      // [nq][trace_cap] expanded nodes in order (index build), or NULL
+    int32_t trace_cap;
     hipStream_t stream;
 };
 

@@ -105,9 +105,13 @@ int launch_search(const SearchArgs &a) {
     p.vis_dist = a.vis_dist;
     p.vis_cnt = a.vis_cnt;
     p.vis_cap = a.vis_cap;
+    p.trace_ids = a.trace_ids;
+    p.trace_cap = a.trace_cap;
     p.self_offset = a.self_offset;
     p.shards = a.shards > 1 ? a.shards : 1;
     p.shard_starts = a.shard_starts;
+    p.init_ids = a.init_n > 0 ? a.init_ids : nullptr;
+    p.init_n = a.init_n > 0 ? a.init_n : 0;
     // learned early stop and feature capture, fused into the search loop
     p.features = a.features;
     p.budget = a.budget;
@@ -147,7 +151,7 @@ int launch_search(const SearchArgs &a) {
         if (cpl == 3) cpl = 4;
         if (cpl > 4) return fail(NSG_EINVAL, "lanes_per_row=%d too small for %d chunks per row", lpr, ix->row_chunks);
     }
-    const bool full = a.vis_ids || a.pool_ids || a.hops || a.ndist || a.nedges || a.self_offset >= 0;
+    const bool full = a.vis_ids || a.pool_ids || a.hops || a.ndist || a.nedges || a.trace_ids || a.self_offset >= 0;
     const int mode = full ? 2 : (a.learned || a.features || a.budget) ? 1 : 0;
     // pool chunks of 64 held in registers (2 * nch registers per lane); the
     // LDS copy of the pool (re-rank sort) keeps the power-of-two L_alloc

@@ -38,6 +38,13 @@ struct KParams {
     // started at shard_starts[i % shards] (shards = 1: one graph, `start`)
     int shards;
     const uint32_t *shard_starts;
+    // random initialization: query i's initial pool is the node set
+    // init_ids[i][0 .. init_n) instead of {start} (init_n = 0: start only)
+    const uint32_t *init_ids;
+    int init_n;
+    // expanded nodes in order, [nq][trace_cap] (all-options variant), or NULL
+    uint32_t *trace_ids;
+    int trace_cap;
     // learned early stop, fused into the search loop (see stop_decide)
     const float *stop_plan;      // network (kernel layout, see stop_decide)
     int32_t *budget;             // chosen budget per query (0: none), or NULL
@@ -267,21 +274,54 @@ search_kernel(KParams p) {
         int vcount = 0;
         const bool rec = FULL && p.vis_ids != nullptr;
 
-        // pool <- {start}
-        if (lane == 0) { cid[0] = start; hash_insert(hash, p.hash_bits, start); }
-        wave_sync();
-        gather_dist<DT, LPR, CPL>(p.tab, qv, sc, cid, cdist, 1, lane);
-        wave_sync();
-        nd = 1;
-        if (rec && lane == 0 && vcount < p.vis_cap) {
-            p.vis_ids[qi * (int64_t)p.vis_cap + vcount] = start;
-            p.vis_dist[qi * (int64_t)p.vis_cap + vcount] = cdist[0];
-        }
-        vcount = 1;
-        const float dstart = cdist[0];
         RegPool<NCH> P;
         rp_init<NCH>(P);
-        rp_insert<NCH>(P, readfirstlane64(mk_key(cdist[0], start)), Lcur, lane);
+        float dstart;
+        if (p.init_n <= 0) {
+            // pool <- {start}
+            if (lane == 0) { cid[0] = start; hash_insert(hash, p.hash_bits, start); }
+            wave_sync();
+            gather_dist<DT, LPR, CPL>(p.tab, qv, sc, cid, cdist, 1, lane);
+            wave_sync();
+            nd = 1;
+            if (rec && lane == 0 && vcount < p.vis_cap) {
+                p.vis_ids[qi * (int64_t)p.vis_cap + vcount] = start;
+                p.vis_dist[qi * (int64_t)p.vis_cap + vcount] = cdist[0];
+            }
+            vcount = 1;
+            dstart = cdist[0];
+            rp_insert<NCH>(P, readfirstlane64(mk_key(cdist[0], start)), Lcur, lane);
+        } else {
+            // pool <- the query's given node set (random initialization),
+            // each node visited once, in batches of 64 through the candidate
+            // arrays; a repeated id is dropped by the filter or the merge
+            const uint32_t *ini = p.init_ids + qrow * (int64_t)p.init_n;
+            for (int b = 0; b < p.init_n; b += 64) {
+                const uint32_t u0 = b + lane < p.init_n ? ini[b + lane] : NSG_SENT;
+                const uint32_t u = u0 < p.tab.n_rows ? u0 : NSG_SENT;
+                const bool nw = u != NSG_SENT && hash_insert(hash, p.hash_bits, u);
+                const uint64_t bm = __ballot(nw);
+                const int rank = __popcll(bm & ((1ull << lane) - 1ull));
+                if (nw) cid[rank] = u;
+                const int cnt = __popcll(bm);
+                wave_sync();
+                if (cnt > 0) {
+                    gather_dist<DT, LPR, CPL>(p.tab, qv, sc, cid, cdist, cnt, lane);
+                    wave_sync();
+                    if (rec)
+                        for (int r = lane; r < cnt; r += 64)
+                            if (vcount + r < p.vis_cap) {
+                                p.vis_ids[qi * (int64_t)p.vis_cap + vcount + r] = cid[r];
+                                p.vis_dist[qi * (int64_t)p.vis_cap + vcount + r] = cdist[r];
+                            }
+                    merge_cands<NCH>(P, cid, cdist, cnt, Lcur, lane);
+                    wave_sync();
+                }
+                nd += cnt;
+                vcount += cnt;
+            }
+            dstart = P.size > 0 ? key_dist(rp_get<NCH>(P, 0)) : 0.0f;
+        }
         for (;;) {
             if (hops >= hcap) break;
             // Algorithm 1: expand the first unchecked pool entry
@@ -291,6 +331,8 @@ search_kernel(KParams p) {
             rp_mark_checked<NCH>(P, i);
             uint32_t v = key_id(pe);
             v = v < p.n_rows ? v : 0u;
+            if (FULL && p.trace_ids && lane == 0 && hops < p.trace_cap)
+                p.trace_ids[qi * (int64_t)p.trace_cap + hops] = v;   // expansion order
             ++hops;
             // neighbour ids (one coalesced row), visited filter, compaction
             const uint32_t *grow = p.graph + (int64_t)v * p.R_pad;

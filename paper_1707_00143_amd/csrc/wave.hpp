@@ -229,22 +229,39 @@ __device__ int merge_pool(uint64_t *pool, int size, int Lcur, uint64_t key, uint
 // ------------------------------------------------------------------------
 // register-resident pool (search)
 // ------------------------------------------------------------------------
-// Lane l of pk[c] holds the key of pool entry 64c + l (KEY_NONE at or beyond
-// size); bit l of the wave-uniform mask chk[c] is that entry's checked flag.
-// The pool is sorted by key, so Algorithm 1's "first unchecked" is a scalar
-// bit scan and an insertion is one compare + ballot per chunk (the rank)
-// followed by a one-lane shift of the chunks at or above it.
+// Lane l of pk[c] holds the key of pool entry 64c + l; bit l of the
+// wave-uniform mask unc[c] is set when that entry is in the pool (position <
+// size) and not yet checked.  The pool is sorted by key, so Algorithm 1's
+// "first unchecked" is a scalar bit scan of unc, and an insertion is one
+// compare + ballot per chunk (the rank) followed by a one-lane shift of the
+// chunks at or above it.
+// Positions at or beyond size hold KEY_NONE until the pool first fills, and
+// afterwards keys pushed out at the end (never read: every reader stops at
+// size).  Such a key is larger than every key in the pool and than every key
+// the merge may still insert (a key enters only below the current L-th key,
+// and the L-th key only decreases), so it never counts in a rank.
 template <int NCH>
 struct RegPool {
     uint64_t pk[NCH];
-    uint64_t chk[NCH];
+    uint64_t unc[NCH];
     int size;
 };
 
+// v_writelane_b32: the wave-uniform `value` replaces lane `lane` of `old`
+// (the compiler intrinsic, bound by name; no builtin is exposed for it)
+__device__ int amdgcn_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 // whole-wave shift by one lane towards higher lanes (lane 0 receives 0)
 __device__ __attribute__((always_inline)) inline uint64_t wave_shr64(uint64_t v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v & 0xFFFFFFFFu), 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)(v & 0xFFFFFFFFu), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, true);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// v with lane l (wave-uniform) replaced by the wave-uniform value x
+__device__ __attribute__((always_inline)) inline uint64_t writelane64(uint64_t v, uint64_t x, int l) {
+    const int lo = amdgcn_writelane((int)(uint32_t)(x & 0xFFFFFFFFu), l, (int)(uint32_t)(v & 0xFFFFFFFFu));
+    const int hi = amdgcn_writelane((int)(uint32_t)(x >> 32), l, (int)(uint32_t)(v >> 32));
     return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
@@ -253,7 +270,7 @@ __device__ __attribute__((always_inline)) inline void rp_init(RegPool<NCH> &P) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         P.pk[c] = KEY_NONE;
-        P.chk[c] = 0ull;
+        P.unc[c] = 0ull;
     }
     P.size = 0;
 }
@@ -278,12 +295,7 @@ template <int NCH>
 __device__ __attribute__((always_inline)) inline int rp_first_unchecked(const RegPool<NCH> &P, uint64_t *key) {
     int pos = -1;
 #pragma unroll
-    for (int c = NCH - 1; c >= 0; --c) {
-        const int n = P.size - (c << 6);
-        const uint64_t valid = n >= 64 ? ~0ull : (n > 0 ? ((1ull << n) - 1ull) : 0ull);
-        const uint64_t um = valid & ~P.chk[c];
-        pos = um ? (c << 6) + __builtin_ctzll(um) : pos;
-    }
+    for (int c = NCH - 1; c >= 0; --c) pos = P.unc[c] ? (c << 6) + __builtin_ctzll(P.unc[c]) : pos;
     if (pos >= 0) *key = rp_get<NCH>(P, pos);
     return pos;
 }
@@ -293,12 +305,12 @@ __device__ __attribute__((always_inline)) inline void rp_mark_checked(RegPool<NC
     const uint64_t bit = 1ull << (pos & 63);
     const int cw = pos >> 6;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) P.chk[c] |= (uint64_t)(cw == c) * bit;
+    for (int c = 0; c < NCH; ++c) P.unc[c] &= cw == c ? ~bit : ~0ull;
 }
 
 // Insert the wave-uniform key s unless the pool holds it (a node the visited
-// filter forgot) or it ranks at or beyond Lcur; entries pushed past Lcur are
-// dropped.  Returns true if inserted.
+// filter forgot) or it ranks at or beyond Lcur; the entry pushed to position
+// Lcur, if any, leaves the pool.  Returns true if inserted.
 template <int NCH>
 __device__ __attribute__((always_inline)) inline bool rp_insert(RegPool<NCH> &P, uint64_t s, int Lcur, int lane) {
     int lt = 0;
@@ -316,22 +328,26 @@ __device__ __attribute__((always_inline)) inline bool rp_insert(RegPool<NCH> &P,
     for (int c = NCH - 1; c >= 0; --c) {
         if ((c << 6) > top || (c << 6) + 63 < lt) continue;
         // chunk c-1 is still unmodified: its last entry moves into lane 0
-        const uint64_t carry = c > 0 ? readlane64(P.pk[c > 0 ? c - 1 : 0], 63) : KEY_NONE;
-        const uint64_t cbit = c > 0 ? (P.chk[c > 0 ? c - 1 : 0] >> 63) : 0ull;
+        // (chunk 0's lane 0 is only ever the inserted key itself)
         uint64_t sh = wave_shr64(P.pk[c]);
-        sh = lane == 0 ? carry : sh;
+        if (c > 0) sh = writelane64(sh, readlane64(P.pk[c > 0 ? c - 1 : 0], 63), 0);
+        const uint64_t cbit = c > 0 ? (P.unc[c > 0 ? c - 1 : 0] >> 63) : 0ull;
         const int idx = (c << 6) + lane;
-        uint64_t nv = idx > lt ? sh : (idx == lt ? s : P.pk[c]);
-        P.pk[c] = idx > top ? KEY_NONE : nv;
         const int lo = lt - (c << 6);
-        const uint64_t f = P.chk[c];
-        if (lo <= 0) {
-            P.chk[c] = (f << 1) | (lo < 0 ? cbit : 0ull);
+        const uint64_t nv = idx >= lt ? sh : P.pk[c];
+        P.pk[c] = lo >= 0 ? writelane64(nv, s, lo) : nv;   // lo <= 63 here
+        const uint64_t f = P.unc[c];
+        uint64_t nf;
+        if (lo < 0) {
+            nf = (f << 1) | cbit;
         } else {
-            const uint64_t below = (1ull << lo) - 1ull;
-            const uint64_t above = ~((2ull << lo) - 1ull);
-            P.chk[c] = (f & below) | ((f << 1) & above);
+            const uint64_t below = (1ull << lo) - 1ull;     // lo <= 63 here
+            nf = (f & below) | ((f << 1) & ~below) | (1ull << lo);
         }
+        // an entry pushed to position Lcur leaves the pool
+        const int cut = Lcur - (c << 6);
+        if (cut < 64) nf &= (1ull << cut) - 1ull;        // cut >= 1 here
+        P.unc[c] = nf;
     }
     P.size = P.size < Lcur ? P.size + 1 : Lcur;
     return true;
@@ -344,7 +360,7 @@ __device__ __attribute__((always_inline)) inline void rp_store(const RegPool<NCH
     for (int c = 0; c < NCH; ++c) {
         const int idx = (c << 6) + lane;
         if ((c << 6) < P.size && idx < P.size)
-            pool[idx] = P.pk[c] | (((P.chk[c] >> lane) & 1ull) ? CHECKED_BIT : 0ull);
+            pool[idx] = P.pk[c] | (((P.unc[c] >> lane) & 1ull) ? 0ull : CHECKED_BIT);
     }
 }
 
