@@ -212,6 +212,10 @@ def main():
             log(f"recall {T}: the learned stop never reaches the target")
             continue
         learned[T] = check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, T, best)
+    if args.target in learned:
+        bq = learn_stop_query(args, nsg, ls, torch, ix16, Tq, ttruth, k, args.target, learned[args.target], nq)
+        if bq is not None:
+            learned[f"q{args.target}"] = check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, args.target, bq)
     if args.target not in learned:
         print(json.dumps({"error": "the learned stop never reaches the target recall"}))
         sys.exit(3)
@@ -303,6 +307,39 @@ def learn_stop(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, L_base, nq_tes
     return best
 
 
+def learn_stop_query(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, base, nq_test):
+    """The query form of the learned stop: inputs are the query's d values,
+    the best distance, the ratio of the 1st to the 10th pool distance and the
+    expansion count at the decision hop (d + 3 -> 64 -> 64 -> 1), with FP16
+    inference fused into the search loop.  Trained on the traces of the pool
+    size and decision hop chosen for the scalar form and calibrated the same
+    way on held-out training queries (from the FP32 forward kernel's
+    predictions)."""
+    L_l, hop = int(base["L"]), int(base["hop"])
+    ntr = Tq.shape[0]
+    n_fit = int(ntr * 0.9)
+    t = time.time()
+    tr = ls.traces(ix16, Tq, ttruth, L_l, k=k, hop=hop)
+    y, _ = ls.labels(tr, k)
+    yh_t = np.maximum(y, np.log2(hop))
+    Xq = ls.query_inputs(Tq, tr.features, hop)
+    P, mean, istd = ls.train(Xq[:n_fit].contiguous(), yh_t[:n_fit], seed=7, epochs=30, log=None)
+    torch.cuda.synchronize()
+    yh = ls.predict(P, mean, istd, Xq[n_fit:].contiguous()).cpu().numpy()
+    hold_mse = float(np.mean((yh - yh_t[n_fit:]) ** 2))
+    base_mse = float(np.mean((yh_t[n_fit:] - yh_t[:n_fit].mean()) ** 2))
+    hits, hops = tr.hits[n_fit:].cpu().numpy(), tr.hops[n_fit:].cpu().numpy()
+    margin = min(0.003, (1.0 - target) / 10)
+    cal = ls.calibrate(yh, hits, tr.grid, k, target, margin=margin, hops=hops, hop=hop)
+    log(f"[{target}] query form, L={L_l} hop {hop}: {Xq.shape[1]} inputs, traces + MLP in {time.time() - t:.1f}s; "
+        f"held-out MSE {hold_mse:.4f} (constant predictor {base_mse:.4f}); calibration {cal}")
+    if not cal:
+        return None
+    return dict(L=L_l, hop=hop, launch=base["launch"], P=P, mean=mean, istd=istd, c=cal[0], grid=list(tr.grid),
+                heldout_mse=hold_mse, const_mse=base_mse, heldout_calibration=cal, kind=nsg.STOP_QUERY,
+                inputs=int(Xq.shape[1]))
+
+
 def check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, target, best):
     """Operating point of the chosen model on the test queries.  The plain
     searches' pool sizes are the smallest reaching the target on the test
@@ -314,7 +351,8 @@ def check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, target, best):
     nq = Qd.shape[0]
 
     def at(c):
-        ls.install(ix16, best["P"], best["mean"], best["istd"], c, best["grid"], hop=best["hop"])
+        ls.install(ix16, best["P"], best["mean"], best["istd"], c, best["grid"], hop=best["hop"],
+                   kind=best.get("kind", 0))
         Bu = torch.empty(nq, dtype=torch.int32, device=dev)
         hq_h = torch.empty(nq, dtype=torch.int64, device=dev)
         ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=best["L"],
@@ -351,9 +389,10 @@ def run_timed(args, z, nsg, ls, torch, dev, w, X, Q, Xd, Qd, ix32, ix16, graph, 
     learned = {}
     for T, m in json.loads(str(z["learned"])).items():
         m = dict(m)
+        key = T if T.startswith("q") else float(T)   # "q<T>": the query form at target T
         for nm in ("P", "mean", "istd"):
-            m[nm] = torch.from_numpy(z[f"{nm}_{float(T)}"]).to(dev)
-        learned[float(T)] = m
+            m[nm] = torch.from_numpy(z[f"{nm}_{key}"]).to(dev)
+        learned[key] = m
     return finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, deg, truth, k, t_knn,
                   t_build, plain, learned, json.loads(str(z["sweep"])))
 
@@ -422,6 +461,21 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
             ms, _ = timed(run, args.steps, args.warmup)
             row["fp16_learned"] = dict(ms=round(ms, 4), qps=round(nq / ms * 1e3, 1), recall10=round(recall(out[0]), 4),
                                        **{a: b for a, b in m.items() if a not in ("P", "mean", "istd", "grid")})
+        mq = learned.get(f"q{T}")
+        if mq:
+            # the query form (query values + three state values, FP16 inference)
+            oq = dict(mq["launch"], learned_stop=1)
+            runq = lambda: nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=int(mq["L"]), out_ids=out[0],
+                                              out_dist=out[1], opts=oq)
+            for cname, c in (("fp16_learned_query_form_heldout_c", mq.get("c_heldout")),
+                             ("fp16_learned_query_form", mq["c"])):
+                if c is None:
+                    continue
+                ls.install(ix16, mq["P"], mq["mean"], mq["istd"], c, mq["grid"], hop=int(mq["hop"]), kind=mq["kind"])
+                ms, _ = timed(runq, args.steps, args.warmup)
+                row[cname] = dict(c=c, ms=round(ms, 4), qps=round(nq / ms * 1e3, 1), recall10=round(recall(out[0]), 4))
+            row["fp16_learned_query_form"].update(
+                {a: b for a, b in mq.items() if a not in ("P", "mean", "istd", "grid", "c")})
         log(f"recall {T}: {row}")
         per_target[T] = row
     head = per_target[args.target]
@@ -520,6 +574,8 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
             "fp16_learned": head["fp16_learned"],
             "plain_fp16": f16row,
             "fp16_learned_heldout_c": head.get("fp16_learned_heldout_c"),
+            "fp16_learned_query_form": head.get("fp16_learned_query_form"),
+            "fp16_learned_query_form_heldout_c": head.get("fp16_learned_query_form_heldout_c"),
             "speedup_vs_plain_fp32": round(qps16 / qps32, 3),
             "speedup_vs_plain_fp16": round(qps16 / f16row["qps"], 3) if f16row else None,
             "speedup_heldout_c_vs_plain_fp32": round(head["fp16_learned_heldout_c"]["qps"] / qps32, 3)
@@ -815,19 +871,42 @@ def ablation(args, torch, nsg, datagen, dev):
     print(json.dumps(res))
 
 
+def knn_graph(nsg, torch, Xd, K, chunk=1_000_000):
+    """Exact K-NN graph (self excluded) in chunks of rows, with a progress
+    line per chunk: each chunk asks for K + 1 neighbours of its rows and drops
+    the row itself (ties at equal distance are ordered by id either way)."""
+    n = Xd.shape[0]
+    if n <= chunk:
+        return nsg.knn_bruteforce(Xd, Xd, K, exclude_self=True)[0]
+    out = torch.empty((n, K), dtype=torch.int32, device=Xd.device)
+    t = time.time()
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        ids, _ = nsg.knn_bruteforce(Xd, Xd[s:e], K + 1)
+        own = torch.arange(s, e, dtype=torch.int32, device=Xd.device).view(-1, 1)
+        keep = ids != own
+        # rows whose own id is absent (K + 1 others at distance 0) keep their first K
+        keep[:, K] &= ~keep.all(1)
+        out[s:e] = ids[keep].view(e - s, K)
+        torch.cuda.synchronize()
+        log(f"exact {K}-NN graph: rows {e} of {n} ({time.time() - t:.0f}s)")
+    return out
+
+
 def uneven(args, torch, nsg, datagen, dev):
     """DEEP-like unit vectors (2000-component mixture, d=96), NSG R=32; a
     stream of 100k queries with k uniform in {1,10,100} and L uniform in
     [10,500], served in batches of 1000 by replaying one captured HIP graph
     of the persistent kernel with the autotuned launch configuration."""
-    n = args.n or 1_000_000
-    w = datagen.scaled(datagen.DEEP10M_LIKE, n, 100_000)
+    n = args.n or datagen.DEEP10M_LIKE.n
+    w = datagen.DEEP10M_LIKE if n == datagen.DEEP10M_LIKE.n else datagen.scaled(datagen.DEEP10M_LIKE, n, 100_000)
     X = datagen.base(w)
     Q = datagen.queries(w)
+    log(f"{w.name}: data {X.shape}")
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
     t = time.time()
-    knn, _ = nsg.knn_bruteforce(Xd, Xd, w.K, exclude_self=True)
+    knn = knn_graph(nsg, torch, Xd, w.K)
     torch.cuda.synchronize()
     log(f"{w.name}: exact {w.K}-NN graph {time.time() - t:.1f}s")
     graph, nav, rep = nsg.build(Xd, knn, w.Lb, w.C, w.R, datagen.random_node(w))
@@ -895,8 +974,9 @@ def uneven(args, torch, nsg, datagen, dev):
 
 
 def precision(args, torch, nsg, datagen, dev):
-    """GIST-like 960-d vectors (500-component mixture, L2-normalised then scaled
-    by U[0.5, 2]), NSG R=70; 1000 queries, k=10.  For each storage format (FP32,
+    """GIST-like 960-d vectors (500-component mixture on a 32-d latent plus
+    noise, L2-normalised then scaled by U[0.5, 2]), NSG R=70; 1000 queries,
+    k=10.  For each storage format (FP32,
     BF16, FP16, E4M3 with per-dimension scales) and pool size: QPS, recall@10
     against the exact top-10, and the largest relative error of the returned
     distances against FP64 distances computed on the host, for the walk's own
@@ -936,7 +1016,7 @@ def precision(args, torch, nsg, datagen, dev):
         return float(np.max(np.abs(dist[ok] - d64) / np.maximum(d64, 1e-30)))
 
     out = {}
-    Ls = (20, 30, 40, 50, 60, 80, 100, 120, 150, 200, 250, 300, 400)
+    Ls = (20, 30, 40, 50, 60, 80, 100, 120, 150, 200, 250, 300, 400, 512)
     for dt in ("f32", "bf16", "f16", "e4m3"):
         ix = nsg.load_index(Xd, graph, nav, dt)
         rows = []
@@ -962,23 +1042,27 @@ def precision(args, torch, nsg, datagen, dev):
         out[dt] = rows
         log(f"{dt}: " + "; ".join(f"L={r['L']} r={r['recall10']} qps={r['qps']:.0f} err {r['max_rel_err_walk']:.1e}/"
                                   f"{r['max_rel_err_rerank']:.1e}" for r in rows))
-    # headline: QPS of each format at the smallest L with recall@10 >= 0.95
-    head = {}
-    for dt, rows in out.items():
-        hit = [r for r in rows if r["recall10"] >= args.target]
-        head[dt] = hit[0] if hit else None
+    # QPS of each format at the smallest L of the sweep reaching each recall
+    # target; the headline is FP16 at the target (0.95 by default) if reached,
+    # else at recall 0.90
+    at = {}
+    for T in sorted({0.90, args.target}):
+        at[str(T)] = {dt: next((r for r in rows if r["recall10"] >= T), None) for dt, rows in out.items()}
+    T_head = str(args.target) if at[str(args.target)]["f16"] else "0.9"
+    head = at[T_head].get("f16")
     res = {
-        "metric": "QPS at recall@10>=0.95 per storage format, 1M x 960 GIST-like, FP32 re-rank",
-        "value": head["f16"]["qps"] if head.get("f16") else None,
-        "unit": "queries/s", "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": None,
+        "metric": f"QPS at recall@10>={T_head}, FP16 storage, 1M x 960 GIST-like, FP32 re-rank "
+                  f"(every format and L in the sweep)",
+        "value": head["qps"] if head else None,
+        "unit": "queries/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+        "ms_per_step": round(nq / head["qps"] * 1e3, 4) if head else None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16 storage, f32 math",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {n} x {X.shape[1]} norm-scaled mixture, {nq} queries, NSG R={w.R} "
+        "config": {"workload": f"{w.name}: {n} x {X.shape[1]} norm-scaled latent mixture, {nq} queries, NSG R={w.R} "
                                f"l={w.Lb} C={w.C} from exact {w.K}-NN graph; k={k}",
-                   "at_target": head, "sweep": out, "knn_s": round(t_knn, 1), "build_s": round(t_build, 1)},
+                   "at_recall": at, "sweep": out, "knn_s": round(t_knn, 1), "build_s": round(t_build, 1),
+                   "repair_edges": rep, "aod": round(float((graph != -1).sum(1).float().mean().item()), 2)},
     }
-    if head.get("f16"):
-        res["ms_per_step"] = round(nq / head["f16"]["qps"] * 1e3, 4)
     print(json.dumps(res))
 
 

@@ -25,7 +25,7 @@ class Workload:
     n_query: int
     n_comp: int
     seed: int
-    kind: str          # "iso" | "latent_clip" | "aniso_clip" | "norm_scaled" | "unit" | "unit_latent"
+    kind: str          # "iso" | "latent_clip" | "aniso_clip" | "norm_scaled" | "norm_scaled_latent" | "unit" | "unit_latent"
     # index parameters (Algorithm 2: K of the kNN graph, l = Lb, m = R, cap C)
     K: int = 100
     R: int = 50
@@ -47,8 +47,15 @@ SIFT1M_LIKE = Workload("sift1m_like_1M_128", 1_000_000, 128, 10_000, 1000, 2, "l
 # the literal reading with independent U[0,255] means (kept for reference)
 SIFT1M_ISLANDS = Workload("sift1m_islands_1M_128", 1_000_000, 128, 10_000, 1000, 2, "aniso_clip",
                           K=100, R=50, Lb=40, C=500)
-# GIST-like: 1M x 960, 500 components, L2-normalised then scaled by U[0.5, 2].
-GIST1M_LIKE = Workload("gist1m_like_1M_960", 1_000_000, 960, 1_000, 500, 3, "norm_scaled",
+# GIST-like: 1M x 960, 500 components, L2-normalised then scaled by U[0.5, 2]
+# per vector.  The component means and the within-component spread live on a
+# 32-dimensional linear latent (GIST1M's local intrinsic dimension is 29.1,
+# Table 1), plus isotropic noise 0.1 in all 960 dimensions.  (Components
+# isotropic in all 960 dimensions, kept as GIST1M_ISO, have an intrinsic
+# dimension near 960.)
+GIST1M_LIKE = Workload("gist1m_like_1M_960", 1_000_000, 960, 1_000, 500, 3, "norm_scaled_latent",
+                       K=100, R=70, Lb=40, C=500)
+GIST1M_ISO = Workload("gist1m_iso_1M_960", 1_000_000, 960, 1_000, 500, 3, "norm_scaled",
                        K=100, R=70, Lb=40, C=500)
 # DEEP-like: 10M x 96 unit-normalised, 2000 components.  The component means
 # and the within-component spread (sigma U[0.25, 1]) live on a 16-dimensional
@@ -88,6 +95,12 @@ def _mixture_params(w: Workload):
     elif w.kind in ("norm_scaled", "unit"):
         means = rng.normal(0.0, 1.0, size=(c, d))
         sig = rng.uniform(0.25, 1.0, size=(c, 1)) * np.ones((1, d))
+    elif w.kind == "norm_scaled_latent":
+        m = 32
+        W = rng.normal(0.0, 1.0 / np.sqrt(m), size=(d, m))
+        means = rng.normal(0.0, 1.0, size=(c, m))            # latent means
+        sig = rng.uniform(0.25, 1.0, size=(c, 1)) * np.ones((1, m))
+        return means, sig, W
     elif w.kind == "unit_latent":
         m = 16
         W = rng.normal(0.0, 1.0 / np.sqrt(m), size=(d, m))
@@ -113,7 +126,7 @@ def _draw(w: Workload, count: int, stream_seed: int, chunk: int = 1 << 16) -> np
             x = means[comp] + sig[comp] * rng.standard_normal(size=(e - s, w.d))
         if w.kind in ("aniso_clip", "latent_clip"):
             np.clip(x, 0.0, 255.0, out=x)
-        elif w.kind == "norm_scaled":
+        elif w.kind in ("norm_scaled", "norm_scaled_latent"):
             x /= np.maximum(np.linalg.norm(x, axis=1, keepdims=True), 1e-30)
             x *= rng.uniform(0.5, 2.0, size=(e - s, 1))
         elif w.kind in ("unit", "unit_latent"):

@@ -314,29 +314,40 @@ int nsg_build_naive(const float *base, int64_t n, int32_t d, const uint32_t *knn
 /* ------------------------------------------------------------------------ */
 
 /*
- * Features (NSG_STOP_FEATURES = 15, FP32), taken from the search state after
- * `hop` expansions; d_r is the distance of pool rank min(r, size - 1) (FP32
- * squared distance of the search format), d_s the distance to the start node:
+ * Two network forms.  In both, the inputs are z-scored with mean[in] /
+ * inv_std[in]; two ReLU hidden layers of h <= 64 units; one linear output
+ * y = predicted log2 of the expansion budget, taken from the search state
+ * after `hop` expansions.  d_r below is the distance of pool rank
+ * min(r, size - 1) (FP32 squared distance of the search format), d_s the
+ * distance to the start node.
+ *
+ * NSG_STOP_SCALAR (in = NSG_STOP_FEATURES = 15 features, FP32 inference):
  *   0 ln(1 + d_0)        1 d_0 / d_9 (1 if d_9 = 0)
  *   2 ln(1 + d_s)        3 ln(1 + d_0) - ln(1 + d_s)
  *   4..13 ln(1 + d_r) - ln(1 + d_0) for r = 1, 2, 4, 9, 14, 19, 29, 39, 59, 83
  *   14 valid neighbour entries read per expansion so far
- * Network: z-scored with mean[in] / inv_std[in] (in = NSG_STOP_FEATURES); two
- * ReLU hidden layers of h <= 64 units; one linear output y = predicted log2
- * of the expansion budget (FP32 throughout).  The query then stops after
- * B = max(hop, smallest grid value >= c * 2^y) expansions (the largest grid
- * value if none is), or earlier when no unchecked entry remains: its result
- * is the plain search's after min(B, its own expansion count) expansions,
- * with the same L.  A non-finite y sets no budget.
- * The decision is fused into the search loop: after expansion `hop` the
- * wavefront forms the features from its pool, evaluates the network and
- * continues with the budget.
- * blob (host) holds FP32: mean[in], inv_std[in], W1[h][in], b1[h],
- * W2[h][h], b2[h], W3[h], b3, then `grid_n` FP32 grid values (expansion
- * counts in [1, 2^20]) ascending.
+ * NSG_STOP_QUERY (in = d + 3, FP16 inference): the query's d values, then
+ *   ln(1 + d_0), d_0 / d_9 (1 if d_9 = 0) and the expansion count.  The
+ *   z-scored inputs (computed in FP32), the weights and the hidden
+ *   activations are rounded to FP16 (nearest even); products accumulate in
+ *   FP32; biases stay FP32.
+ *
+ * The query then stops after B = max(hop, smallest grid value >= c * 2^y)
+ * expansions (the largest grid value if none is), or earlier when no
+ * unchecked entry remains: its result is the plain search's after
+ * min(B, its own expansion count) expansions, with the same L.  A
+ * non-finite y sets no budget.  The decision is fused into the search loop:
+ * after expansion `hop` the wavefront forms the inputs from its pool and its
+ * query, evaluates the network and continues with the budget.
+ * blob (host) holds FP32 in both forms: mean[in], inv_std[in], W1[h][in],
+ * b1[h], W2[h][h], b2[h], W3[h], b3, then `grid_n` FP32 grid values
+ * (expansion counts in [1, 2^20]) ascending.  Errors: NSG_EINVAL for a
+ * wrong kind, input width or blob size, or a grid out of range.
  */
 #define NSG_STOP_FEATURES 15
-int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes,
+#define NSG_STOP_SCALAR 0
+#define NSG_STOP_QUERY 1
+int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes, int32_t kind,
                         int32_t in, int32_t h, int32_t hop, int32_t grid_n);
 
 /* Enable (1) or disable (0) the early stop and set its calibration c > 0.

@@ -448,6 +448,39 @@ def stop_features(pool_dist, d_start, nedges, hops):
     return np.asarray(f, np.float64)
 
 
+def stop_query_inputs(q, pool_dist, hops):
+    """Inputs of the query form of the early stop (the library's own
+    definition, FP64): the query's d values, then ln(1 + d_0), d_0 / d_9
+    (1 if d_9 = 0; d_r at rank min(r, size - 1)) and the expansion count."""
+    f = stop_features(pool_dist, 0.0, 0, hops)
+    return np.concatenate([np.asarray(q, np.float64), [f[0], f[1], float(hops)]])
+
+
+def _fp16(a):
+    """Round to FP16, nearest even, through FP32 (as values held in FP32 are)."""
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float16).astype(np.float64)
+
+
+def mlp_forward_fp16(params, X, n_in, h):
+    """The network with FP16 inference (the early stop's query form): the
+    inputs X [B][n_in] (already z-scored), the weights W1, W2, W3 and the
+    hidden activations after each ReLU are rounded to FP16; every product and
+    sum is taken in FP64; the biases b1, b2, b3 are used as given.  Params
+    layout W1[h][n_in], b1[h], W2[h][h], b2[h], W3[h], b3.  Returns yhat [B]."""
+    P = np.asarray(params, np.float64)
+    o = 0
+    W1 = P[o:o + h * n_in].reshape(h, n_in); o += h * n_in
+    b1 = P[o:o + h]; o += h
+    W2 = P[o:o + h * h].reshape(h, h); o += h * h
+    b2 = P[o:o + h]; o += h
+    W3 = P[o:o + h]; o += h
+    b3 = P[o]
+    x = _fp16(np.atleast_2d(X))
+    a1 = _fp16(np.maximum(x @ _fp16(W1).T + b1, 0.0))
+    a2 = _fp16(np.maximum(a1 @ _fp16(W2).T + b2, 0.0))
+    return a2 @ _fp16(W3) + b3
+
+
 def recall_at_k(found_ids, gt_ids, k):
     """precision(R') = |R' ∩ R| / K (Sec. 2.1 Eq. 1), per query; padding is a miss."""
     found_ids = np.asarray(found_ids)[:, :k]

@@ -33,6 +33,8 @@ class NSGError(RuntimeError):
 
 
 STOP_FEATURES = 15   # early-stop features per query (see nsg.h)
+STOP_SCALAR = 0      # network forms of the early stop (see nsg.h)
+STOP_QUERY = 1
 
 
 class SearchOpts(ctypes.Structure):
@@ -85,7 +87,7 @@ def _load():
         "nsg_knn_bruteforce": (i32, [P, i64, P, i64, i32, i32, i32, P, P, P]),
         "nsg_build": (i32, [P, i64, i32, P, i32, i32, i32, i32, u32, P, P, P, P]),
         "nsg_build_naive": (i32, [P, i64, i32, P, i32, i32, P, P]),
-        "nsg_load_stop_model": (i32, [P, P, ctypes.c_size_t, i32, i32, i32, i32]),
+        "nsg_load_stop_model": (i32, [P, P, ctypes.c_size_t, i32, i32, i32, i32, i32]),
         "nsg_set_stop_mode": (i32, [P, i32, f32]),
         "nsg_mlp_forward_backward": (i32, [P, i32, i32, P, P, i64, P, P, P, P]),
         "nsg_mlp_adam": (i32, [P, P, P, P, i64, i64, f32, f32, f32, f32, P]),
@@ -327,10 +329,11 @@ def build_naive(base, knn, R, stream=None):
     return g
 
 
-def load_stop_model(index: Index, blob: bytes, n_in: int, h: int, hop: int, grid_n: int):
-    """nsg_load_stop_model: blob = FP32 mean, inv_std, W1, b1, W2, b2, W3, b3, grid."""
+def load_stop_model(index: Index, blob: bytes, n_in: int, h: int, hop: int, grid_n: int, kind: int = 0):
+    """nsg_load_stop_model: blob = FP32 mean, inv_std, W1, b1, W2, b2, W3, b3, grid.
+    kind STOP_SCALAR (15 scalar features) or STOP_QUERY (query + 3 state values)."""
     buf = ctypes.create_string_buffer(blob, len(blob))
-    _call("nsg_load_stop_model", index.handle, buf, len(blob), int(n_in), int(h), int(hop), int(grid_n))
+    _call("nsg_load_stop_model", index.handle, buf, len(blob), int(kind), int(n_in), int(h), int(hop), int(grid_n))
 
 
 def set_stop_mode(index: Index, enabled: bool, calib_c: float = 1.0):

@@ -375,14 +375,16 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
 // ---------------------------------------------------------------------------
 // learned early stop: model residency
 // ---------------------------------------------------------------------------
-extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes, int32_t in, int32_t h,
-                                   int32_t hop, int32_t grid_n) {
+extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes, int32_t kind, int32_t in,
+                                   int32_t h, int32_t hop, int32_t grid_n) {
     clear_error();
     if (!idx || !blob) return fail(NSG_EINVAL, "NULL index or blob");
     if (idx->stop_graphs.load() > 0)
         return fail(NSG_ESTATE, "%d search graph(s) captured with the early stop still use the model",
                     idx->stop_graphs.load());
-    if (in != kStopFeatures) return fail(NSG_EINVAL, "model input %d must be %d features", in, kStopFeatures);
+    if (kind != NSG_STOP_SCALAR && kind != NSG_STOP_QUERY) return fail(NSG_EINVAL, "unknown model kind %d", kind);
+    const int want_in = kind == NSG_STOP_SCALAR ? kStopFeatures : idx->d + 3;
+    if (in != want_in) return fail(NSG_EINVAL, "model input %d must be %d for this kind", in, want_in);
     if (h < 1 || h > 64) return fail(NSG_EUNSUPPORTED, "hidden width %d outside [1, 64]", h);
     if (hop < 1) return fail(NSG_EINVAL, "hop must be >= 1");
     if (grid_n < 1 || grid_n > 256) return fail(NSG_EINVAL, "grid_n out of range [1, 256]");
@@ -394,19 +396,36 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
         if (!(grid[i] >= 1.0f && grid[i] <= 1048576.0f)) return fail(NSG_EINVAL, "grid value out of [1, 2^20]");
         if (i && grid[i] <= grid[i - 1]) return fail(NSG_EINVAL, "grid must be strictly ascending");
     }
-    // kernel layout: W1T[in][64], W2T[64][64], b1[64], b2[64], W3[64], b3,
-    // mean[in], inv_std[in], grid[grid_n] (hidden units past h are zero)
+    // kernel layout of the form (hidden units past h are zero):
+    //  scalar: W1T[in][64], W2T[64][64], b1[64], b2[64], W3[64], b3, mean[in], inv_std[in], grid
+    //  query:  W1[(in+1)/2][64] and W2[32][64] as FP16 pairs, then the same FP32 tail (W3 FP16-rounded)
     const float *mean = b, *istd = b + in, *W1 = istd + in, *b1 = W1 + (size_t)h * in, *W2 = b1 + h;
     const float *b2 = W2 + (size_t)h * h, *W3 = b2 + h, *b3 = W3 + h;
-    std::vector<float> pl((size_t)in * 64 + 64 * 64 + 3 * 64 + 1 + 2 * (size_t)in + grid_n, 0.0f);
-    float *pW1T = pl.data(), *pW2T = pW1T + (size_t)in * 64, *pb1 = pW2T + 64 * 64, *pb2 = pb1 + 64;
+    const size_t w1_words = kind == NSG_STOP_SCALAR ? (size_t)in * 64 : (size_t)((in + 1) / 2) * 64;
+    const size_t w2_words = kind == NSG_STOP_SCALAR ? 64 * 64 : 32 * 64;
+    std::vector<float> pl(w1_words + w2_words + 3 * 64 + 1 + 2 * (size_t)in + grid_n, 0.0f);
+    float *pW1T = pl.data(), *pW2T = pW1T + w1_words, *pb1 = pW2T + w2_words, *pb2 = pb1 + 64;
     float *pW3 = pb2 + 64, *pb3 = pW3 + 64, *pmean = pb3 + 1, *pistd = pmean + in, *pgrid = pistd + in;
+    auto f16 = [](float v) -> uint16_t { return __builtin_bit_cast(uint16_t, (_Float16)v); };
     for (int j = 0; j < h; ++j) {
-        for (int i = 0; i < in; ++i) pW1T[(size_t)i * 64 + j] = W1[(size_t)j * in + i];
-        for (int k = 0; k < h; ++k) pW2T[(size_t)k * 64 + j] = W2[(size_t)j * h + k];
+        if (kind == NSG_STOP_SCALAR) {
+            for (int i = 0; i < in; ++i) pW1T[(size_t)i * 64 + j] = W1[(size_t)j * in + i];
+            for (int k = 0; k < h; ++k) pW2T[(size_t)k * 64 + j] = W2[(size_t)j * h + k];
+            pW3[j] = W3[j];
+        } else {
+            uint32_t *w1 = reinterpret_cast<uint32_t *>(pW1T), *w2 = reinterpret_cast<uint32_t *>(pW2T);
+            for (int i = 0; i < in; i += 2) {
+                const uint32_t hi = i + 1 < in ? f16(W1[(size_t)j * in + i + 1]) : 0u;
+                w1[(size_t)(i / 2) * 64 + j] = f16(W1[(size_t)j * in + i]) | hi << 16;
+            }
+            for (int k = 0; k < h; k += 2) {
+                const uint32_t hi = k + 1 < h ? f16(W2[(size_t)j * h + k + 1]) : 0u;
+                w2[(size_t)(k / 2) * 64 + j] = f16(W2[(size_t)j * h + k]) | hi << 16;
+            }
+            pW3[j] = (float)(_Float16)W3[j];
+        }
         pb1[j] = b1[j];
         pb2[j] = b2[j];
-        pW3[j] = W3[j];
     }
     *pb3 = *b3;
     for (int i = 0; i < in; ++i) {
@@ -421,6 +440,7 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
         hipFree(sm.blob);
         return fail(NSG_EDEVICE, "model copy failed: %s", hipGetErrorString(e));
     }
+    sm.kind = kind;
     sm.in = in;
     sm.h = h;
     sm.hop = hop;

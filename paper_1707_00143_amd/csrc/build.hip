@@ -19,6 +19,7 @@
 #include "wave.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -460,7 +461,15 @@ extern "C" int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t
         NSG_HIP(hipStreamSynchronize(st));
         return NSG_OK;
     };
+    auto t_log = std::chrono::steady_clock::now();
+    int64_t batches = 0;
     for (;;) {
+        if (log_on && std::chrono::steady_clock::now() - t_log > std::chrono::seconds(10)) {
+            t_log = std::chrono::steady_clock::now();
+            BUILD_LOG("repair: %lld batches, %lld edges added, next unreached id >= %lld", (long long)batches,
+                      (long long)added, (long long)scan);
+        }
+        ++batches;
         // the next SB unreached nodes in id order, searched together
         cand.clear();
         for (int64_t v = scan; v < n && (int64_t)cand.size() < SB; ++v)

@@ -39,8 +39,8 @@ void clear_error();
 constexpr int kStopFeatures = 15;
 
 struct StopModel {
-    float *blob = nullptr;     // device FP32, kernel layout: W1T[in][64], W2T[64][64], b1[64], b2[64],
-                               // W3[64], b3, mean[in], inv_std[in], grid[grid_n] (units past h zero)
+    float *blob = nullptr;     // device, the kernel layout of the network form (see stop_decide)
+    int kind = NSG_STOP_SCALAR;
     int in = 0, h = 0, hop = 0, grid_n = 0;
     int enabled = 0;
     float calib_c = 1.0f;

@@ -125,6 +125,7 @@ int launch_search(const SearchArgs &a) {
         p.learned = 1;
         p.stop_plan = sm.blob;
         p.s_in = sm.in;
+        p.s_kind = sm.kind;
         p.s_hop = sm.hop;
         p.grid_n = sm.grid_n;
         p.calib_c = sm.calib_c;

@@ -50,6 +50,7 @@ struct KParams {
     int32_t *budget;             // chosen budget per query (0: none), or NULL
     float *features;             // raw features [nq][kStopFeatures] after expansion s_hop, or NULL
     int s_in, s_hop, grid_n;
+    int s_kind;                  // network form: NSG_STOP_SCALAR or NSG_STOP_QUERY
     float calib_c;
     int learned;                 // 1: queries with L >= 16 stop at their budget
 };
@@ -148,23 +149,101 @@ __device__ inline float stop_feature(int i, DistAt dist, int size, float dstart,
     return hops > 0 ? (float)ne / (float)hops : 0.0f;
 }
 
+// The budget for network output o: smallest grid value >= c * 2^o (the
+// largest if none is), at least the decision hop; -1 / 0 for a non-finite o.
+__device__ inline int stop_budget(const float *grid, int grid_n, float calib_c, int hop, float o, int lane,
+                                  int *B) {
+    const float t = calib_c * exp2f(o);
+    if (!isfinite(t)) { *B = 0; return -1; }
+    int gi = grid_n - 1;
+    for (int b = 0; b < grid_n; b += 64) {
+        const int i = b + lane;
+        const uint64_t bm = __ballot(i < grid_n && grid[i] >= t);
+        if (bm) { gi = b + __ffsll((long long)bm) - 1; break; }
+    }
+    const int v = (int)grid[gi];
+    *B = v < hop ? hop : v;
+    return gi;
+}
+
+typedef _Float16 half2_v __attribute__((ext_vector_type(2)));
+
+__device__ inline uint32_t pack_half2(float a, float b) {
+    const half2_v v = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// sum + a.x * b.x + a.y * b.y: FP16 operands, FP32 accumulation (v_dot2_f32_f16)
+__device__ inline float dot2_h(uint32_t a, uint32_t b, float sum) {
+    return __builtin_amdgcn_fdot2(__builtin_bit_cast(half2_v, a), __builtin_bit_cast(half2_v, b), sum, false);
+}
+
 // The learned stop's decision for one query, after the decision hop: the
 // features of its pool (pool[0 .. size) in LDS), the raw features to
-// `features` (if given), then, if `plan` is given, the network (W1T[in][64],
-// W2T[64][64], b1[64], b2[64], W3[64], b3, mean[in], inv_std[in],
-// grid[grid_n]; hidden units past h are zero).  Returns the grid index of the
-// budget (-1: no budget for a non-finite output) and the budget in *B (at
-// least hop; 0 for none).  Not inlined: it runs once per query and would
-// otherwise hold registers through the whole search loop.
-__device__ __attribute__((noinline)) int stop_decide(const float *plan, int in, int grid_n, float calib_c, int hop,
-                                                     const uint64_t *pool, int size, float dstart, int64_t ne,
-                                                     int64_t hops, float *features, int lane, int *B) {
+// `features` (if given), then, if `plan` is given, the network and the
+// budget.  Returns the grid index of the budget (-1: no budget for a
+// non-finite output) and the budget in *B (at least hop; 0 for none).  Not
+// inlined: it runs once per query and would otherwise hold registers through
+// the whole search loop.  Lane j evaluates hidden unit j (units past h have
+// zero weights); inputs and first-layer outputs reach every lane by lane
+// reads; the transposed weights are read coalesced.
+//  kind NSG_STOP_SCALAR, FP32: the kStopFeatures scalar features.  Plan:
+//    W1T[in][64], W2T[64][64], b1[64], b2[64], W3[64], b3, mean[in],
+//    inv_std[in], grid[grid_n].
+//  kind NSG_STOP_QUERY, FP16 inference: inputs = the query's d values, then
+//    ln(1 + d_0), d_0 / d_9 and the expansion count; z-scored in FP32 and
+//    rounded to FP16, like the weights and the hidden activations; products
+//    accumulate in FP32.  Plan (32-bit words): W1[(in + 1) / 2][64] (FP16
+//    pairs: inputs 2i, 2i + 1 of unit j), W2[32][64] (FP16 pairs: units 2i,
+//    2i + 1), b1[64], b2[64] (FP32), W3[64] (FP16 values held in FP32), b3,
+//    mean[in], inv_std[in], grid[grid_n].
+__device__ __attribute__((noinline)) int stop_decide(const float *plan, int kind, int in, int grid_n,
+                                                     float calib_c, int hop, const uint64_t *pool, int size,
+                                                     float dstart, int64_t ne, int64_t hops, const float *q, int d,
+                                                     float *features, int lane, int *B) {
     float f = 0.0f;
     if (lane < kStopFeatures)
         f = stop_feature(lane, [&](int r) { return key_dist(pool[r]); }, size, dstart, ne, hops);
     if (features && lane < kStopFeatures) features[lane] = f;
     *B = 0;
     if (!plan) return -1;
+    float o;
+    if (kind == NSG_STOP_QUERY) {
+        const uint32_t *W1 = reinterpret_cast<const uint32_t *>(plan);
+        const int np1 = (in + 1) >> 1;
+        const uint32_t *W2 = W1 + (size_t)np1 * 64;
+        const float *b1 = reinterpret_cast<const float *>(W2 + 32 * 64), *b2 = b1 + 64, *W3 = b2 + 64;
+        const float *b3 = W3 + 64, *mean = b3 + 1, *istd = mean + in, *grid = istd + in;
+        const float d0 = key_dist(pool[0]), d9 = key_dist(pool[size > 9 ? 9 : size - 1]);
+        auto input = [&](int i) -> float {
+            const float v = i < d ? q[i] : (i == d ? log1pf(d0) : (i == d + 1 ? (d9 > 0.0f ? d0 / d9 : 1.0f)
+                                                                               : (float)hops));
+            return (v - mean[i]) * istd[i];
+        };
+        float s1 = b1[lane];
+        for (int r = 0; r < np1; r += 64) {
+            // lane l packs the input pair r + l
+            const int pi = r + lane;
+            uint32_t xw = 0;
+            if (pi < np1) xw = pack_half2(input(2 * pi), 2 * pi + 1 < in ? input(2 * pi + 1) : 0.0f);
+            const int cnt = np1 - r < 64 ? np1 - r : 64;
+            for (int t = 0; t < cnt; ++t)
+                s1 = dot2_h(W1[(size_t)(r + t) * 64 + lane], __builtin_amdgcn_readlane(xw, t), s1);
+        }
+        const float a1 = s1 > 0.0f ? s1 : 0.0f;
+        // lane l < 32 packs hidden units 2l, 2l + 1
+        const int l2 = 2 * (lane & 31);
+        const uint32_t aw = pack_half2(__shfl(a1, l2), __shfl(a1, l2 + 1));
+        float s2 = b2[lane];
+#pragma unroll 8
+        for (int t = 0; t < 32; ++t) s2 = dot2_h(W2[t * 64 + lane], __builtin_amdgcn_readlane(aw, t), s2);
+        const float a2 = (float)(_Float16)(s2 > 0.0f ? s2 : 0.0f);
+        o = W3[lane] * a2;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) o += __shfl_xor(o, off);
+        o += b3[0];
+        return stop_budget(grid, grid_n, calib_c, hop, o, lane, B);
+    }
     const float *W1T = plan;
     const float *W2T = W1T + in * 64, *b1 = W2T + 64 * 64, *b2 = b1 + 64, *W3 = b2 + 64, *b3 = W3 + 64;
     const float *mean = b3 + 1, *istd = mean + in, *grid = istd + in;
@@ -182,21 +261,11 @@ __device__ __attribute__((noinline)) int stop_decide(const float *plan, int in, 
         s2 = fmaf(W2T[k * 64 + lane], ak, s2);
     }
     const float a2 = s2 > 0.0f ? s2 : 0.0f;
-    float o = W3[lane] * a2;
+    o = W3[lane] * a2;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) o += __shfl_xor(o, off);
     o += b3[0];
-    const float t = calib_c * exp2f(o);
-    if (!isfinite(t)) { *B = 0; return -1; }
-    int gi = grid_n - 1;   // smallest grid value >= t, else the largest
-    for (int b = 0; b < grid_n; b += 64) {
-        const int i = b + lane;
-        const uint64_t bm = __ballot(i < grid_n && grid[i] >= t);
-        if (bm) { gi = b + __ffsll((long long)bm) - 1; break; }
-    }
-    const int v = (int)grid[gi];
-    *B = v < hop ? hop : v;
-    return gi;
+    return stop_budget(grid, grid_n, calib_c, hop, o, lane, B);
 }
 
 // MODE selects what is compiled in: 0 the plain search only; 1 also the
@@ -370,8 +439,9 @@ search_kernel(KParams p) {
                 decide = false;
                 rp_store<NCH>(P, pool, lane);
                 wave_sync();
-                stop_decide(learn_q ? p.stop_plan : nullptr, p.s_in, p.grid_n, p.calib_c, p.s_hop, pool, P.size,
-                            dstart, ne, hops, p.features ? p.features + qi * kStopFeatures : nullptr, lane, &Bq);
+                stop_decide(learn_q ? p.stop_plan : nullptr, p.s_kind, p.s_in, p.grid_n, p.calib_c, p.s_hop, pool,
+                            P.size, dstart, ne, hops, q, p.d, p.features ? p.features + qi * kStopFeatures : nullptr,
+                            lane, &Bq);
                 Bq = __builtin_amdgcn_readfirstlane(Bq);
                 if (Bq > 0 && Bq < hcap) hcap = Bq;
                 wave_sync();

@@ -12,7 +12,10 @@ Features are 15 scalars of the search state after the decision expansion
 node, neighbour entries per expansion; STOP_FEATURES in the library), the
 same in every run, so one capture serves every grid point.  The network (15 -> 64 -> 64 -> 1,
 ReLU) is trained with the library's forward/backward and Adam kernels on
-z-scored features; the calibration constant c is the smallest one whose
+z-scored features.  A second form takes the query itself plus three state
+values (best distance, ratio of the 1st to the 10th pool distance, expansion
+count; d + 3 -> 64 -> 64 -> 1) and runs with FP16 inference in the search
+loop (query_inputs, kind=STOP_QUERY).  The calibration constant c is the smallest one whose
 held-out mean recall meets the target when each query's budget is the grid
 value at or above c * 2^y.  At search time the decision is fused into the
 search loop of every query.
@@ -24,7 +27,7 @@ import dataclasses
 import numpy as np
 import torch
 
-from . import (STOP_FEATURES, column_stats, load_stop_model, mlp_adam, mlp_forward, mlp_forward_backward, recall_hits,
+from . import (STOP_FEATURES, STOP_QUERY, STOP_SCALAR, column_stats, load_stop_model, mlp_adam, mlp_forward, mlp_forward_backward, recall_hits,
                search_batched, set_stop_mode)
 
 GRID = [int(round(16 * 2 ** (i / 4))) for i in range(25)]   # 16, 19, 23, ..., 1024 expansions
@@ -78,6 +81,17 @@ def features_at(index, queries, L, hop, k=10, chunk=50_000):
         search_batched(index, queries[s:e], k_scalar=k, L_scalar=L,
                        opts=dict(max_hops=hop, features=feats[s:e], feature_hop=hop))
     return feats
+
+
+def query_inputs(queries, features, hop=HOP):
+    """Inputs of the query form: the query's d values, ln(1 + d_0), d_0 / d_9
+    (features 0 and 1 of the capture) and the expansion count at the decision
+    (the decision hop); NaN rows (search ended before the hop) stay NaN."""
+    nq = queries.shape[0]
+    h = torch.full((nq, 1), float(hop), dtype=torch.float32, device=queries.device)
+    X = torch.cat([queries.float(), features[:, :2], h], 1)
+    X[torch.isnan(features[:, 0])] = float("nan")
+    return X.contiguous()
 
 
 def labels(tr: Traces, k=10):
@@ -186,7 +200,7 @@ def model_blob(P, mean, istd, grid):
     return np.concatenate([p.astype(np.float32).ravel() for p in parts]).tobytes()
 
 
-def install(index, P, mean, istd, c, grid=GRID, hop=HOP):
+def install(index, P, mean, istd, c, grid=GRID, hop=HOP, kind=STOP_SCALAR):
     n_in = mean.numel()
-    load_stop_model(index, model_blob(P, mean, istd, grid), n_in, HIDDEN, hop, len(grid))
+    load_stop_model(index, model_blob(P, mean, istd, grid), n_in, HIDDEN, hop, len(grid), kind=kind)
     set_stop_mode(index, True, c)

@@ -233,6 +233,47 @@ def test_uneven_stream_batch_parity():
     ix.close()
 
 
+def test_uneven_stream_10M_sampled_parity():
+    """The uneven-batch path at the configuration's full size (DEEP-like 10M x
+    96): a batch of 1000 queries with per-query k in {1,10,100} and L in
+    [10,500], replayed from a captured HIP graph of the persistent launch, on
+    a seeded random 32-regular graph over all 10M rows (search parity does
+    not need a good graph; this one makes every query touch rows spread over
+    the whole 3.8 GB table), equals the oracle's Algorithm 1 at each query's
+    (k, L) on 250 sampled queries."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_00143_amd as nsg
+    dev = torch.device("cuda:0")
+    w = datagen.DEEP10M_LIKE
+    X = datagen.base(w)
+    Q = datagen.queries(w)[:1000]
+    print(f"10M uneven fixture: {w.name}, base {X.shape}", flush=True)
+    n = X.shape[0]
+    G = np.random.default_rng(2024).integers(0, n, size=(n, 32), dtype=np.uint32)
+    nav = int(np.random.default_rng(2025).integers(0, n))
+    Xd = torch.from_numpy(X).to(dev)
+    ix = nsg.load_index(Xd, torch.from_numpy(G.view(np.int32)).to(dev), nav, "f32")
+    kk, LL = datagen.uneven_kL(100_000, w.seed + 5)
+    kk, LL = kk[:1000], LL[:1000]
+    Qd = torch.from_numpy(Q).to(dev)
+    kd, Ld = torch.from_numpy(kk).to(dev), torch.from_numpy(LL).to(dev)
+    g = nsg.SearchGraph(ix, Qd, k=kd, L=Ld, L_scalar=500, out_stride=100, opts=dict(persistent=1))
+    ids, dist = g.launch()
+    torch.cuda.synchronize()
+    print("10M uneven: batch searched", flush=True)
+    ids, dist = _np(ids).view(np.uint32).copy(), _np(dist).copy()
+    sel = np.arange(0, 1000, 4)
+    for i in sel:                             # entries past k[i] are not part of the result
+        ids[i, kk[i]:] = 0xFFFFFFFF
+        dist[i, kk[i]:] = np.inf
+    o_ids, _, _, _ = oracle.search(X, G, nav, Q[sel], 100, 500, k_arr=kk[sel], L_arr=LL[sel], threads=16)
+    r = compare(X, Q[sel], ids[sel], dist[sel], o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+    g.close()
+    ix.close()
+
+
 @pytest.fixture(scope="module")
 def gist():
     if not torch.cuda.is_available():

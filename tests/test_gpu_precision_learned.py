@@ -208,6 +208,87 @@ def test_learned_stop_every_format_and_pool_size(nsg, tiny_index, dt, L, hop):
     ix.close()
 
 
+def _grid_pick(t, grid, hop):
+    g = np.asarray(grid, np.float64)
+    i = min(int(np.searchsorted(g, t, side="left")), len(g) - 1)
+    return int(max(g[i], hop))
+
+
+@pytest.mark.parametrize("dt,L,hop", [("f16", 60, 16), ("f32", 92, 16), ("e4m3", 200, 32)])
+def test_query_form_learned_stop_matches_oracle(nsg, tiny_index, dt, L, hop):
+    """The query form of the learned stop (the query's values plus three
+    state values, FP16 inference fused into the search loop): each query's
+    budget equals the pick of the oracle's FP16-inference network on the
+    oracle's inputs at the decision hop (a pick may differ by one grid step
+    only where c * 2^y lies within 0.5 % of a grid value), and with those
+    budgets the walk equals the oracle's Algorithm 1 over the decoded rows
+    and the output the oracle's FP32 re-rank of its pool."""
+    dev = _dev()
+    import math
+    from paper_1707_00143_amd import learned_stop as ls
+    X, G, nav, Q = tiny_index["X"], tiny_index["graph"], tiny_index["nav"], tiny_index["Q"]
+    ix = nsg.load_index(torch.from_numpy(X).to(dev), torch.from_numpy(G.view(np.int32)).to(dev), nav, dt)
+    Qd = torch.from_numpy(Q).to(dev)
+    nq, k, H = len(Q), 10, ls.HIDDEN
+    # a random network on z-scored inputs, its output spread around the plain
+    # search's mean expansion count (about half the searches are cut)
+    feats = torch.empty((nq, nsg.STOP_FEATURES), dtype=torch.float32, device=dev)
+    hp = torch.zeros(nq, dtype=torch.int64, device=dev)
+    nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(features=feats, feature_hop=hop))
+    nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(hops=hp))
+    Xin = ls.query_inputs(Qd, feats, hop)
+    n_in = Xin.shape[1]
+    assert n_in == X.shape[1] + 3
+    keep = ~torch.isnan(Xin).any(1)
+    mean, istd = nsg.column_stats(Xin[keep].contiguous())
+    m32, s32 = _np(mean), _np(istd)
+    P = ls.init_params(n_in, H, 11).astype(np.float64)
+    z = (_np(Xin[keep]) - m32) * s32
+    y = oracle.mlp_forward_fp16(P, z, n_in, H)
+    sd = float(y.std()) or 1.0
+    P[-(H + 1):-1] *= 1.2 / sd
+    P[-1] = (P[-1] - float(y.mean())) * 1.2 / sd + math.log2(float(hp.float().mean().item()))
+    P = P.astype(np.float32)
+    with pytest.raises(nsg.NSGError):     # the scalar form's width is not this form's
+        nsg.load_stop_model(ix, ls.model_blob(torch.from_numpy(P), mean, istd, ls.GRID), nsg.STOP_FEATURES, H,
+                            hop, len(ls.GRID), kind=nsg.STOP_QUERY)
+    ls.install(ix, torch.from_numpy(P).to(dev), mean, istd, 1.0, hop=hop, kind=nsg.STOP_QUERY)
+    Bu = torch.zeros(nq, dtype=torch.int32, device=dev)
+    ids, dist = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(learned_stop=1, budget=Bu))
+    wi, wd = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(learned_stop=1, rerank=-1))
+    Bu = _np(Bu)
+    # the oracle's inputs at the decision hop, its network, its pick
+    Xt = X if dt == "f32" else oracle.quantize(dt, X, oracle.scales(dt, X))[1]
+    _, _, oh, _, opids, opd = oracle.search(Xt, G, nav, Q, k, L, pool_stride=L, max_hops=hop)
+    P64 = P.astype(np.float64)
+    ties = 0
+    for i in range(nq):
+        if oh[i] < hop:                  # ended before the decision hop: no budget
+            assert Bu[i] == 0, i
+            continue
+        v = opids[i] != oracle.SENT
+        x = oracle.stop_query_inputs(Q[i], opd[i][v], hop).astype(np.float32)
+        zi = (x - m32) * s32
+        yo = float(oracle.mlp_forward_fp16(P64, zi, n_in, H)[0])
+        t = 2.0 ** yo
+        want = _grid_pick(t, ls.GRID, hop)
+        if Bu[i] != want:
+            near = min(abs(t / g - 1.0) for g in ls.GRID)
+            adj = {_grid_pick(t * 0.995, ls.GRID, hop), _grid_pick(t * 1.005, ls.GRID, hop)}
+            assert near < 5e-3 and int(Bu[i]) in adj, (i, int(Bu[i]), want, t)
+            ties += 1
+    assert ties <= max(1, nq // 50), ties
+    assert len(set(Bu.tolist())) > 3 and set(Bu.tolist()) <= set(ls.GRID) | {0}
+    o_ids, _, o_hops, _, o_pids, _ = oracle.search(Xt, G, nav, Q, k, L, pool_stride=L, max_hops=Bu)
+    assert 0 < (o_hops == Bu).sum() < nq              # some searches cut by the budget, some not
+    r = compare(Xt, Q, _np(wi).view(np.uint32), _np(wd), o_ids)
+    assert r["ok"], (dt, L, {a: b for a, b in r.items() if a != "bad"}, r["bad"][:3])
+    rr_ids = o_ids if dt == "f32" else oracle.rerank(X, Q, o_pids, k)[0]
+    r = compare(X, Q, _np(ids).view(np.uint32), _np(dist), rr_ids)
+    assert r["ok"], (dt, L, {a: b for a, b in r.items() if a != "bad"}, r["bad"][:3])
+    ix.close()
+
+
 def test_max_hops_matches_oracle(nsg, tiny_index):
     """A caller-given expansion budget equals the oracle's Algorithm 1 stopped
     after that many expansions (FP32, several budgets in one batch)."""

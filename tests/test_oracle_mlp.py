@@ -89,3 +89,58 @@ def test_stop_features_worked_example():
     # degenerate: a one-entry pool at distance 0 and no expansions
     g = oracle.stop_features(np.zeros(1, np.float32), 0.0, 0, 0)
     assert g[1] == 1.0 and g[14] == 0.0 and (g[[0, 2, 3]] == 0).all() and (g[4:14] == 0).all()
+
+
+def test_fp16_forward_equals_fp64_forward_on_representable_values():
+    """With the query form's shape (131 -> 64 -> 64 -> 1), integer inputs and
+    weights in {-1, 0, 1} (8 nonzero first-layer weights per unit) and small
+    integer biases, every input, weight and hidden activation is an integer
+    below 2048 in magnitude, exact in FP16: the FP16-inference forward then
+    equals the FP64 forward of the oracle's C code."""
+    n_in, h = 131, 64
+    rng = np.random.default_rng(3)
+    W1 = np.zeros((h, n_in))
+    for j in range(h):
+        W1[j, rng.choice(n_in, 8, replace=False)] = rng.choice([-1.0, 1.0], 8)
+    b1 = rng.integers(-2, 3, size=h).astype(float)
+    W2 = rng.integers(-1, 2, size=(h, h)).astype(float)
+    b2 = rng.integers(-2, 3, size=h).astype(float)
+    W3 = rng.integers(-1, 2, size=h).astype(float)
+    P = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3, [0.5]])
+    assert P.size == oracle.mlp_nparams(n_in, h)
+    X = rng.integers(-1, 2, size=(8, n_in)).astype(float)
+    _, _, want = oracle.mlp_loss_grad(P, X, None, n_in, h)
+    got = oracle.mlp_forward_fp16(P, X, n_in, h)
+    assert np.abs(want).max() > 4 and len(set(want.tolist())) > 4
+    assert (got == want).all(), (got, want)
+
+
+def test_fp16_forward_rounding_points():
+    """1 -> 1 -> 1 -> 1 networks: the input, the weights and each hidden
+    activation are rounded to FP16 to nearest, ties to even (spacing 2^-10
+    just above 1), overflow gives inf, ReLU clips negatives; biases are not
+    rounded."""
+    def net(w1=1.0, b1=0.0, w2=1.0, b2=0.0, w3=1.0, b3=0.0):
+        return np.array([w1, b1, w2, b2, w3, b3])
+
+    f = lambda P, x: float(oracle.mlp_forward_fp16(P, np.array([[x]]), 1, 1)[0])
+    u = 2.0 ** -10
+    assert f(net(), 1 + u / 2) == 1.0                    # tie -> even (1)
+    assert f(net(), 1 + 3 * u / 2) == 1 + 2 * u          # tie -> even (1 + 2u)
+    assert f(net(), 1 + 0.6 * u) == 1 + u                # nearest
+    assert f(net(), 7e4) == math.inf                     # beyond FP16's largest finite value
+    assert f(net(), -3.0) == 0.0
+    assert f(net(w1=1 + u / 2), 1.0) == 1.0              # weight rounded
+    assert f(net(b1=u / 2), 1.0) == 1.0                  # first activation rounded (1 + u/2 -> 1)
+    assert f(net(b2=u / 2), 1.0) == 1.0                  # second activation rounded
+    assert f(net(b3=u / 4), 1.0) == 1 + u / 4            # output bias not rounded
+    assert f(net(w3=-1 - u / 2), 1.0) == -1.0            # output weight rounded
+
+
+def test_query_form_inputs():
+    q = np.array([1.5, -2.0, 0.25], np.float32)
+    x = oracle.stop_query_inputs(q, np.arange(3, 15, dtype=np.float32), 16)
+    assert x.shape == (6,)
+    assert (x[:3] == q).all() and x[3] == math.log(4.0) and x[4] == 3.0 / 12.0 and x[5] == 16.0
+    y = oracle.stop_query_inputs(q, np.array([0.0], np.float32), 0)
+    assert (y[3:] == [0.0, 1.0, 0.0]).all()
