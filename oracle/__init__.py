@@ -77,6 +77,7 @@ def _get():
             "oracle_search_batch": (i32, [P, i64, i32, P, i32, u32, P, i64, i32, i32, P, P,
                                           i32, P, P, P, P, P, P, i32, P, P, P, i32, i32]),
             "oracle_build_naive": (i32, [P, i64, i32, P, i32, i32, P]),
+            "oracle_knn_ivf": (i32, [P, i64, i32, P, i32, i32, i32, P, P, P]),
             "oracle_search_one": (i32, [P, i64, i32, P, i32, u32, P, i32, i64, P, P, P,
                                         P, i64, P, P, i64, P]),
             "oracle_centroid": (i32, [P, i64, i32, P]),
@@ -317,6 +318,21 @@ def build_nsg(base, knn_g, Lb, C, m, rand_start, threads=0):
                                    int(m), int(rand_start), _p(g), _p(nav), _p(stats),
                                    int(threads)), "build_nsg")
     return g, int(nav[0]), int(stats[0])
+
+
+def knn_ivf(base, pivots, nprobe, K, return_probes=False):
+    """Approximate kNN graph by an inverted file over the pivot points
+    base[pivots]: row i = the K nearest (FP32 key, id) among the other points
+    whose cell (nearest pivot) is one of i's nprobe nearest pivots.  Returns
+    (ids [n][K] uint32, dists [n][K] float32[, probes [n][nprobe]])."""
+    base, pivots = _f32(base), _u32(pivots)
+    n, d = base.shape
+    ids = np.empty((n, K), np.uint32)
+    dist = np.empty((n, K), np.float32)
+    pr = np.empty((n, nprobe), np.uint32)
+    _check(_get().oracle_knn_ivf(_p(base), n, d, _p(pivots), len(pivots), int(nprobe), int(K), _p(ids), _p(dist),
+                                 _p(pr)), "knn_ivf")
+    return (ids, dist, pr) if return_probes else (ids, dist)
 
 
 def build_naive(base, knn_g, m):

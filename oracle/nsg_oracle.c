@@ -121,6 +121,101 @@ int oracle_knn(const float *base, int64_t n, int d, const float *queries,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Approximate kNN graph by an inverted file: step (i) of the build, which    */
+/* the paper leaves replaceable (nn-descent on CPU; Faiss on GPU for          */
+/* DEEP100M, Sec. 3.5 indexing complexity).                                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Cells: the nlist pivot points base[pivots[c]].  The probes of point i are
+ * its nprobe nearest pivots, ordered by (FP32 squared distance, c); its cell
+ * is its first probe.  Row i of the graph: the K points nearest to i by
+ * (FP32 squared distance, id) among the points other than i whose cell is
+ * one of i's probes.  Output ids[n][K] (SENT padded), dists[n][K] (FP32 keys,
+ * +inf padded), and, if probes_out is given, the probes [n][nprobe].
+ * Returns 0, -1 on bad arguments, -2 on allocation failure.
+ */
+int oracle_knn_ivf(const float *base, int64_t n, int d, const uint32_t *pivots, int nlist, int nprobe,
+                   int K, uint32_t *ids, float *dists, uint32_t *probes_out)
+{
+    if (n < 1 || d < 1 || nlist < 1 || nprobe < 1 || nprobe > nlist || nprobe > 160 || K < 1) return -1;
+    for (int c = 0; c < nlist; ++c)
+        if ((int64_t)pivots[c] >= n) return -1;
+    uint32_t *probe = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n * nprobe);
+    int64_t *start = (int64_t *)calloc((size_t)nlist + 1, sizeof(int64_t));
+    uint32_t *member = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    if (!probe || !start || !member) { free(probe); free(start); free(member); return -2; }
+    int bad = 0;
+    /* probes: the nprobe nearest pivots of every point */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const float *x = base + i * (int64_t)d;
+        dkey_t top[160];
+        int cnt = 0;
+        for (int c = 0; c < nlist; ++c) {
+            double key = (double)oracle_l2sq_f32(x, base + (int64_t)pivots[c] * d, d);
+            uint32_t id = (uint32_t)c;
+            if (cnt == nprobe && !dkey_less(key, id, top[nprobe - 1].key, top[nprobe - 1].id)) continue;
+            int pos = cnt < nprobe ? cnt : nprobe - 1;
+            while (pos > 0 && dkey_less(key, id, top[pos - 1].key, top[pos - 1].id)) {
+                top[pos] = top[pos - 1];
+                --pos;
+            }
+            top[pos].key = key;
+            top[pos].id = id;
+            if (cnt < nprobe) ++cnt;
+        }
+        for (int j = 0; j < nprobe; ++j) probe[i * nprobe + j] = top[j].id;
+    }
+    /* members of every cell, in id order */
+    for (int64_t i = 0; i < n; ++i) start[probe[i * nprobe] + 1]++;
+    for (int c = 0; c < nlist; ++c) start[c + 1] += start[c];
+    {
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)nlist);
+        if (!fill) bad = 2;
+        else {
+            for (int c = 0; c < nlist; ++c) fill[c] = start[c];
+            for (int64_t i = 0; i < n; ++i) member[fill[probe[i * nprobe]]++] = (uint32_t)i;
+            free(fill);
+        }
+    }
+    /* every point: exact K nearest among the members of its probed cells */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        if (bad) continue;
+        dkey_t *top = (dkey_t *)malloc(sizeof(dkey_t) * (size_t)K);
+        if (!top) { bad = 2; continue; }
+        int cnt = 0;
+        const float *x = base + i * (int64_t)d;
+        for (int j = 0; j < nprobe; ++j) {
+            uint32_t c = probe[i * nprobe + j];
+            for (int64_t t = start[c]; t < start[c + 1]; ++t) {
+                uint32_t id = member[t];
+                if ((int64_t)id == i) continue;
+                double key = (double)oracle_l2sq_f32(x, base + (int64_t)id * d, d);
+                if (cnt == K && !dkey_less(key, id, top[K - 1].key, top[K - 1].id)) continue;
+                int pos = cnt < K ? cnt : K - 1;
+                while (pos > 0 && dkey_less(key, id, top[pos - 1].key, top[pos - 1].id)) {
+                    top[pos] = top[pos - 1];
+                    --pos;
+                }
+                top[pos].key = key;
+                top[pos].id = id;
+                if (cnt < K) ++cnt;
+            }
+        }
+        for (int j = 0; j < K; ++j) {
+            ids[i * K + j] = j < cnt ? top[j].id : SENT;
+            dists[i * K + j] = j < cnt ? (float)top[j].key : INFINITY;
+        }
+        free(top);
+    }
+    if (probes_out && !bad) memcpy(probes_out, probe, sizeof(uint32_t) * (size_t)n * nprobe);
+    free(probe); free(start); free(member);
+    return bad ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Algorithm 1, Search-on-Graph(G, p, q, l)                                  */
 /* ------------------------------------------------------------------------ */
 

@@ -273,11 +273,16 @@ __device__ __attribute__((noinline)) int stop_decide(const float *plan, int kind
 // option (visited recording, pool output, counters, own-row visit).  Options
 // left out keep registers free for occupancy.
 // NCH: pool chunks of 64 held in registers (NCH * 64 >= the pool capacity).
-// Occupancy targets for the common 2-chunk pool: the plain search at 5 waves
-// per SIMD (<= 96 registers; a few cold values go to scratch, measured
-// faster), the learned-stop variant too.
+// Occupancy target: 5 waves per SIMD (<= 96 registers; a few cold values go
+// to scratch, measured faster) for the 2-chunk pool when the query and its
+// scales take at most 32 registers per lane (FP32 up to 4 chunks per lane,
+// FP16 / BF16 up to 2); otherwise none, since wider queries would spill most
+// of the loop's state.
+template <int DT, int CPL>
+constexpr int query_regs() { return CPL * Fmt<DT>::EPC * (DT == NSG_F32 ? 1 : 2); }
 template <int DT, int LPR, int CPL, int MODE, int NCH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 2 ? (MODE <= 1 ? 5 : 1) : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    NCH == 2 && MODE <= 1 && DT != NSG_E4M3 && query_regs<DT, CPL>() <= 32 ? 5 : 1)))
 search_kernel(KParams p) {
     constexpr int EPC = Fmt<DT>::EPC;
     constexpr bool FULL = MODE == 2;
