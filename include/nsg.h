@@ -299,6 +299,25 @@ int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t *knn,
               void *stream);
 
 /*
+ * Approximate kNN graph by an inverted file (step (i) of the build, which the
+ * paper leaves replaceable: nn-descent on the CPU, Faiss on the GPU for
+ * DEEP100M; Sec. 3.5, indexing complexity).  Cells are the nlist pivot
+ * points base[pivots[c]] (pivots: device, nlist ids < n, chosen by the
+ * caller, e.g. a seeded random sample); a point's probes are its nprobe
+ * nearest pivots by (FP32 squared distance, c) and its cell the nearest.
+ * Row i of the output: the K points nearest to i by (FP32 squared distance,
+ * id) among the points other than i whose cell is one of i's probes
+ * (sentinel / +inf padded when there are fewer).  nprobe = nlist gives the
+ * exact kNN graph.  out_ids [n][K], out_dist [n][K] (device).  Limits:
+ * 1 <= nlist <= n, 1 <= nprobe <= min(nlist, 160), 1 <= K <= 159,
+ * n * nprobe < 2^31.  Temporary device memory ≈ n (8 K + 24 nprobe + 24)
+ * bytes plus the largest cell's rows.  Synchronous.
+ */
+int nsg_knn_ivf(const float *base, int64_t n, int32_t d, const uint32_t *pivots,
+                int32_t nlist, int32_t nprobe, int32_t K, uint32_t *out_ids,
+                float *out_dist, void *stream);
+
+/*
  * NSG-Naive, the baseline of Sec. 4.1.2: the MRNG edge selection of Algorithm
  * 2 applied to each node's own kNN list only (candidates = the K neighbours
  * of knn[n][K], sorted by (distance, id)), at most R edges per node; no

@@ -88,6 +88,7 @@ def _load():
         "nsg_build": (i32, [P, i64, i32, P, i32, i32, i32, i32, u32, P, P, P, P]),
         "nsg_build_naive": (i32, [P, i64, i32, P, i32, i32, P, P]),
         "nsg_load_stop_model": (i32, [P, P, ctypes.c_size_t, i32, i32, i32, i32, i32]),
+        "nsg_knn_ivf": (i32, [P, i64, i32, P, i32, i32, i32, P, P, P]),
         "nsg_set_stop_mode": (i32, [P, i32, f32]),
         "nsg_mlp_forward_backward": (i32, [P, i32, i32, P, P, i64, P, P, P, P]),
         "nsg_mlp_adam": (i32, [P, P, P, P, i64, i64, f32, f32, f32, f32, P]),
@@ -303,6 +304,19 @@ def knn_bruteforce(base, queries, k, exclude_self=False, stream=None):
     _call("nsg_knn_bruteforce", _dev(base, torch.float32, "base"), n, _dev(queries, torch.float32, "queries"),
           nq, d, int(k), 1 if exclude_self else 0, _dev(ids, torch.int32, "ids"),
           _dev(dist, torch.float32, "dist"), _stream(stream))
+    return ids, dist
+
+
+def knn_ivf(base, pivots, nprobe, K, stream=None):
+    """nsg_knn_ivf: approximate kNN graph by an inverted file over the pivot
+    rows base[pivots] (pivots int32 device tensor).  Returns (ids int32
+    [n][K], dist float32 [n][K])."""
+    n, d = base.shape
+    ids = torch.empty((n, K), dtype=torch.int32, device=base.device)
+    dist = torch.empty((n, K), dtype=torch.float32, device=base.device)
+    _call("nsg_knn_ivf", _dev(base, torch.float32, "base"), n, d, _dev(pivots, torch.int32, "pivots"),
+          int(pivots.numel()), int(nprobe), int(K), _dev(ids, torch.int32, "ids"), _dev(dist, torch.float32, "dist"),
+          _stream(stream))
     return ids, dist
 
 

@@ -1,0 +1,65 @@
+"""GPU parity of the inverted-file approximate kNN graph (nsg_knn_ivf)
+against the oracle's definition: probes by the pivots, exact top K among the
+members of the probed cells."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SENT = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def nsg():
+    import paper_1707_00143_amd as m
+    return m
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("n,nlist,nprobe,K", [(20_000, 40, 3, 32), (20_000, 40, 1, 100), (3_000, 600, 2, 12)])
+def test_ivf_graph_matches_oracle(nsg, n, nlist, nprobe, K):
+    dev = _dev()
+    w = datagen.scaled(datagen.DEEP10M_LIKE, n, 10)
+    X = datagen.base(w)
+    piv = np.random.default_rng(n + nlist).choice(n, nlist, replace=False).astype(np.uint32)
+    ids, dist = nsg.knn_ivf(torch.from_numpy(X).to(dev), torch.from_numpy(piv.view(np.int32)).to(dev), nprobe, K)
+    ids, dist = ids.cpu().numpy().view(np.uint32), dist.cpu().numpy()
+    o_ids, o_dist = oracle.knn_ivf(X, piv, nprobe, K)
+    pad = o_ids == SENT
+    assert ((ids == SENT) == pad).mean() > 0.999          # padding where a probed set has fewer than K others
+    r = compare(X, X, ids, dist, o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+
+
+def test_all_cells_probed_is_the_exact_graph(nsg):
+    dev = _dev()
+    w = datagen.scaled(datagen.DEEP10M_LIKE, 8_000, 10)
+    X = datagen.base(w)
+    Xd = torch.from_numpy(X).to(dev)
+    piv = torch.from_numpy(np.random.default_rng(3).choice(len(X), 16, replace=False).astype(np.int32)).to(dev)
+    ids, dist = nsg.knn_ivf(Xd, piv, 16, 40)
+    e_ids, e_dist = nsg.knn_bruteforce(Xd, Xd, 40, exclude_self=True)
+    assert torch.equal(ids, e_ids) and torch.equal(dist, e_dist)
+
+
+def test_bad_arguments_rejected(nsg):
+    dev = _dev()
+    X = torch.rand((100, 8), device=dev)
+    good = torch.arange(4, dtype=torch.int32, device=dev)
+    with pytest.raises(nsg.NSGError):
+        nsg.knn_ivf(X, torch.tensor([0, 5, 100], dtype=torch.int32, device=dev), 1, 4)   # pivot id >= n
+    with pytest.raises(nsg.NSGError):
+        nsg.knn_ivf(X, good, 5, 4)                                                        # nprobe > nlist
+    with pytest.raises(nsg.NSGError):
+        nsg.knn_ivf(X, good, 2, 160)                                                      # K > 159
