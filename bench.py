@@ -66,7 +66,9 @@ def measured_traffic(kernel):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    return int(t["traffic_bytes"]) if t.get("src_sha256") == source_sha256() else None
+    if t.get("src_sha256") != source_sha256():
+        return None
+    return int(t["traffic_bytes"]), f"{t.get('kernel')}: {t.get('workload')}"
 
 
 def log(msg):
@@ -530,8 +532,9 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
     ach16 = b16 / (ms16 / 1e3) / 1e9
     ach32 = b32 / (ms32 / 1e3) / 1e9
     lpr = int(m["launch"].get("lanes_per_row") or 8)
+    tr16, tr32 = measured_traffic("f16_learned"), measured_traffic("f32")
     roof = dict(bound="hbm", achieved=round(ach16, 1), peak=8000.0, unit="GB/s", frac=round(ach16 / 8000.0, 4),
-                traffic=measured_traffic("f16_learned"),
+                traffic=tr16[0] if tr16 else None, traffic_measured_on=tr16[1] if tr16 else None,
                 kernel=f"search_kernel<F16, lanes per row {lpr}, chunks per lane {max(1, -(-(rb16 // 16) // lpr))}, "
                        f"learned stop, {2 if L16 <= 128 else 4 if L16 <= 256 else 6 if L16 <= 384 else 8} pool chunks>",
                 launch=m["launch"], bytes_per_launch=int(b16), ms_per_launch=ms16,
@@ -539,7 +542,7 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
                 counts=counts["source"])
     lpr32 = int(launch32.get("lanes_per_row") or 8)
     roof32 = dict(bound="hbm", achieved=round(ach32, 1), peak=8000.0, unit="GB/s", frac=round(ach32 / 8000.0, 4),
-                  traffic=measured_traffic("f32"),
+                  traffic=tr32[0] if tr32 else None, traffic_measured_on=tr32[1] if tr32 else None,
                   kernel=f"search_kernel<F32, lanes per row {lpr32}, chunks per lane {-(-(d // 4) // lpr32)}, plain, "
                          f"2 pool chunks>", launch=launch32, bytes_per_launch=int(b32), ms_per_launch=round(ms32, 4),
                   per_query={a: round(v / nq, 2) for a, v in counts["f32"].items()}, counts=counts["source"])
