@@ -220,7 +220,13 @@ def main():
     if args.target in learned:
         bq = learn_stop_query(args, nsg, ls, torch, ix16, Tq, ttruth, k, args.target, learned[args.target], nq)
         if bq is not None:
+            bm = learn_stop_checkpoints(args, nsg, ls, torch, ix16, Tq, k, args.target, bq)
+            for key in ("traces", "y"):
+                bq.pop(key)
             learned[f"q{args.target}"] = check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, args.target, bq)
+            if bm is not None:
+                learned[f"qm{args.target}"] = check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k,
+                                                            args.target, bm)
     if args.target not in learned:
         print(json.dumps({"error": "the learned stop never reaches the target recall"}))
         sys.exit(3)
@@ -342,7 +348,40 @@ def learn_stop_query(args, nsg, ls, torch, ix16, Tq, ttruth, k, target, base, nq
         return None
     return dict(L=L_l, hop=hop, launch=base["launch"], P=P, mean=mean, istd=istd, c=cal[0], grid=list(tr.grid),
                 heldout_mse=hold_mse, const_mse=base_mse, heldout_calibration=cal, kind=nsg.STOP_QUERY,
-                inputs=int(Xq.shape[1]))
+                inputs=int(Xq.shape[1]), traces=tr, y=y)
+
+
+def learn_stop_checkpoints(args, nsg, ls, torch, ix16, Tq, k, target, base_q, cps=None):
+    """The query form deciding at several checkpoints (hop, 2 hop, 4 hop): one
+    network trained on the inputs taken at every checkpoint (the expansion
+    count input tells them apart; targets max(label, log2 checkpoint)), each
+    query's budget replaced at every checkpoint it still runs past, c
+    calibrated on held-out training queries by replaying those decisions on
+    the traces."""
+    L_l, hop, tr, y = int(base_q["L"]), int(base_q["hop"]), base_q["traces"], base_q["y"]
+    cps = cps or [hop, 2 * hop, 4 * hop]
+    ntr = Tq.shape[0]
+    n_fit = int(ntr * 0.9)
+    t = time.time()
+    Xs, ys, valid, Xh = [], [], [], []
+    for cp in cps:
+        f = tr.features if cp == hop else ls.features_at(ix16, Tq, L_l, cp, k=k)
+        Xq = ls.query_inputs(Tq, f, cp)
+        Xs.append(Xq[:n_fit])
+        ys.append(np.maximum(y[:n_fit], np.log2(cp)))
+        valid.append(~torch.isnan(Xq[n_fit:, 0]).cpu().numpy())
+        Xh.append(Xq[n_fit:].contiguous())
+    P, mean, istd = ls.train(torch.cat(Xs).contiguous(), np.concatenate(ys), seed=7, epochs=30, log=None)
+    torch.cuda.synchronize()
+    yhats = [ls.predict(P, mean, istd, x).cpu().numpy() for x in Xh]
+    hits, hops = tr.hits[n_fit:].cpu().numpy(), tr.hops[n_fit:].cpu().numpy()
+    margin = min(0.003, (1.0 - target) / 10)
+    cal = ls.calibrate_checkpoints(yhats, valid, hits, tr.grid, cps, hops, k, target, margin=margin)
+    log(f"[{target}] query form, checkpoints {cps}, L={L_l}: trained in {time.time() - t:.1f}s; calibration {cal}")
+    if not cal:
+        return None
+    return dict(L=L_l, hop=hop, checkpoints=list(cps), launch=base_q["launch"], P=P, mean=mean, istd=istd, c=cal[0],
+                grid=list(tr.grid), heldout_calibration=cal, kind=nsg.STOP_QUERY, inputs=int(Xh[0].shape[1]))
 
 
 def check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, target, best):
@@ -357,7 +396,7 @@ def check_on_test(args, nsg, ls, torch, dev, ix16, Qd, truth, k, target, best):
 
     def at(c):
         ls.install(ix16, best["P"], best["mean"], best["istd"], c, best["grid"], hop=best["hop"],
-                   kind=best.get("kind", 0))
+                   kind=best.get("kind", 0), checkpoints=best.get("checkpoints"))
         Bu = torch.empty(nq, dtype=torch.int32, device=dev)
         hq_h = torch.empty(nq, dtype=torch.int64, device=dev)
         ids, _ = nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=best["L"],
@@ -394,7 +433,7 @@ def run_timed(args, z, nsg, ls, torch, dev, w, X, Q, Xd, Qd, ix32, ix16, graph, 
     learned = {}
     for T, m in json.loads(str(z["learned"])).items():
         m = dict(m)
-        key = T if T.startswith("q") else float(T)   # "q<T>": the query form at target T
+        key = T if T.startswith("q") else float(T)   # "q<T>" / "qm<T>": the query form (checkpoints) at target T
         for nm in ("P", "mean", "istd"):
             m[nm] = torch.from_numpy(z[f"{nm}_{key}"]).to(dev)
         learned[key] = m
@@ -466,21 +505,23 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
             ms, _ = timed(run, args.steps, args.warmup)
             row["fp16_learned"] = dict(ms=round(ms, 4), qps=round(nq / ms * 1e3, 1), recall10=round(recall(out[0]), 4),
                                        **{a: b for a, b in m.items() if a not in ("P", "mean", "istd", "grid")})
-        mq = learned.get(f"q{T}")
-        if mq:
-            # the query form (query values + three state values, FP16 inference)
+        for mkey, label in ((f"q{T}", "fp16_learned_query_form"), (f"qm{T}", "fp16_learned_query_form_checkpoints")):
+            # the query form (query values + three state values, FP16
+            # inference), with one decision or several checkpoints
+            mq = learned.get(mkey)
+            if not mq:
+                continue
             oq = dict(mq["launch"], learned_stop=1)
             runq = lambda: nsg.search_batched(ix16, Qd, k_scalar=k, L_scalar=int(mq["L"]), out_ids=out[0],
                                               out_dist=out[1], opts=oq)
-            for cname, c in (("fp16_learned_query_form_heldout_c", mq.get("c_heldout")),
-                             ("fp16_learned_query_form", mq["c"])):
+            for cname, c in ((label + "_heldout_c", mq.get("c_heldout")), (label, mq["c"])):
                 if c is None:
                     continue
-                ls.install(ix16, mq["P"], mq["mean"], mq["istd"], c, mq["grid"], hop=int(mq["hop"]), kind=mq["kind"])
+                ls.install(ix16, mq["P"], mq["mean"], mq["istd"], c, mq["grid"], hop=int(mq["hop"]), kind=mq["kind"],
+                           checkpoints=mq.get("checkpoints"))
                 ms, _ = timed(runq, args.steps, args.warmup)
                 row[cname] = dict(c=c, ms=round(ms, 4), qps=round(nq / ms * 1e3, 1), recall10=round(recall(out[0]), 4))
-            row["fp16_learned_query_form"].update(
-                {a: b for a, b in mq.items() if a not in ("P", "mean", "istd", "grid", "c")})
+            row[label].update({a: b for a, b in mq.items() if a not in ("P", "mean", "istd", "grid", "c")})
         log(f"recall {T}: {row}")
         per_target[T] = row
     head = per_target[args.target]
@@ -582,6 +623,8 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
             "fp16_learned_heldout_c": head.get("fp16_learned_heldout_c"),
             "fp16_learned_query_form": head.get("fp16_learned_query_form"),
             "fp16_learned_query_form_heldout_c": head.get("fp16_learned_query_form_heldout_c"),
+            "fp16_learned_query_form_checkpoints": head.get("fp16_learned_query_form_checkpoints"),
+            "fp16_learned_query_form_checkpoints_heldout_c": head.get("fp16_learned_query_form_checkpoints_heldout_c"),
             "speedup_vs_plain_fp32": round(qps16 / qps32, 3),
             "speedup_vs_plain_fp16": round(qps16 / f16row["qps"], 3) if f16row else None,
             "speedup_heldout_c_vs_plain_fp32": round(head["fp16_learned_heldout_c"]["qps"] / qps32, 3)

@@ -369,6 +369,19 @@ int nsg_build_naive(const float *base, int64_t n, int32_t d, const uint32_t *knn
 int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t bytes, int32_t kind,
                         int32_t in, int32_t h, int32_t hop, int32_t grid_n);
 
+/*
+ * Decision checkpoints of the loaded model (host array of n ints, 1 <= n <= 4,
+ * strictly ascending, each in [1, 65535]; hops[0] becomes the model's decision
+ * hop).  After expansion hops[j] a query still allowed to run past it forms
+ * the inputs again, evaluates the network and replaces its budget by
+ * max(hops[j], the grid pick); the next checkpoint is taken only if the new
+ * budget lets the search pass it.  With the query form the expansion count
+ * input then differs between checkpoints.  Loading a model resets the list
+ * to its hop.  NSG_ESTATE without a model or while a search graph captured
+ * with the early stop exists.
+ */
+int nsg_set_stop_checkpoints(nsg_index *idx, const int32_t *hops, int32_t n);
+
 /* Enable (1) or disable (0) the early stop and set its calibration c > 0.
  * Both this call and nsg_load_stop_model return NSG_ESTATE while a search
  * graph captured with the early stop exists on the index (see above). */

@@ -89,6 +89,7 @@ def _load():
         "nsg_build_naive": (i32, [P, i64, i32, P, i32, i32, P, P]),
         "nsg_load_stop_model": (i32, [P, P, ctypes.c_size_t, i32, i32, i32, i32, i32]),
         "nsg_knn_ivf": (i32, [P, i64, i32, P, i32, i32, i32, P, P, P]),
+        "nsg_set_stop_checkpoints": (i32, [P, P, i32]),
         "nsg_set_stop_mode": (i32, [P, i32, f32]),
         "nsg_mlp_forward_backward": (i32, [P, i32, i32, P, P, i64, P, P, P, P]),
         "nsg_mlp_adam": (i32, [P, P, P, P, i64, i64, f32, f32, f32, f32, P]),
@@ -348,6 +349,12 @@ def load_stop_model(index: Index, blob: bytes, n_in: int, h: int, hop: int, grid
     kind STOP_SCALAR (15 scalar features) or STOP_QUERY (query + 3 state values)."""
     buf = ctypes.create_string_buffer(blob, len(blob))
     _call("nsg_load_stop_model", index.handle, buf, len(blob), int(kind), int(n_in), int(h), int(hop), int(grid_n))
+
+
+def set_stop_checkpoints(index: Index, hops):
+    """nsg_set_stop_checkpoints: decision checkpoints (1 to 4 ascending expansion counts)."""
+    arr = (ctypes.c_int32 * len(hops))(*[int(h) for h in hops])
+    _call("nsg_set_stop_checkpoints", index.handle, arr, len(hops))
 
 
 def set_stop_mode(index: Index, enabled: bool, calib_c: float = 1.0):

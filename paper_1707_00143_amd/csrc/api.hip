@@ -323,7 +323,7 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     if (o.pool_ids && (o.pool_stride < 1 || !o.pool_dist)) return fail(NSG_EINVAL, "pool output needs stride and dist");
     if (o.learned_stop < 0 || o.learned_stop > 1) return fail(NSG_EINVAL, "learned_stop must be 0 or 1");
     if (o.learned_stop && !stop_ready(idx)) return fail(NSG_ESTATE, "no early-stop model loaded and enabled");
-    if (o.feature_hop < 0) return fail(NSG_EINVAL, "feature_hop < 0");
+    if (o.feature_hop < 0 || o.feature_hop > 65535) return fail(NSG_EINVAL, "feature_hop out of [0, 65535]");
     if (o.max_hops < 0) return fail(NSG_EINVAL, "max_hops < 0");
     if (o.lanes_per_row && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
         o.lanes_per_row != 64)
@@ -386,7 +386,7 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
     const int want_in = kind == NSG_STOP_SCALAR ? kStopFeatures : idx->d + 3;
     if (in != want_in) return fail(NSG_EINVAL, "model input %d must be %d for this kind", in, want_in);
     if (h < 1 || h > 64) return fail(NSG_EUNSUPPORTED, "hidden width %d outside [1, 64]", h);
-    if (hop < 1) return fail(NSG_EINVAL, "hop must be >= 1");
+    if (hop < 1 || hop > 65535) return fail(NSG_EINVAL, "hop must be in [1, 65535]");
     if (grid_n < 1 || grid_n > 256) return fail(NSG_EINVAL, "grid_n out of range [1, 256]");
     const size_t nf = (size_t)2 * in + (size_t)h * in + h + (size_t)h * h + h + h + 1 + grid_n;
     if (bytes != nf * sizeof(float)) return fail(NSG_EINVAL, "blob has %zu bytes, expected %zu", bytes, nf * 4);
@@ -443,6 +443,8 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
     sm.kind = kind;
     sm.in = in;
     sm.h = h;
+    sm.ncp = 1;
+    sm.cps[0] = hop;
     sm.hop = hop;
     sm.grid_n = grid_n;
     sm.enabled = idx->stop.enabled;
@@ -450,6 +452,24 @@ extern "C" int nsg_load_stop_model(nsg_index *idx, const void *blob, size_t byte
     hipDeviceSynchronize();
     hipFree(idx->stop.blob);
     idx->stop = sm;
+    return NSG_OK;
+}
+
+extern "C" int nsg_set_stop_checkpoints(nsg_index *idx, const int32_t *hops, int32_t n) {
+    clear_error();
+    if (!idx || !hops) return fail(NSG_EINVAL, "NULL index or checkpoints");
+    if (!idx->stop.blob) return fail(NSG_ESTATE, "no early-stop model loaded");
+    if (idx->stop_graphs.load() > 0)
+        return fail(NSG_ESTATE, "%d search graph(s) captured with the early stop hold its checkpoints",
+                    idx->stop_graphs.load());
+    if (n < 1 || n > 4) return fail(NSG_EINVAL, "%d checkpoints, expected 1 to 4", n);
+    for (int c = 0; c < n; ++c) {
+        if (hops[c] < 1 || hops[c] > 65535) return fail(NSG_EINVAL, "checkpoint %d out of [1, 65535]", hops[c]);
+        if (c && hops[c] <= hops[c - 1]) return fail(NSG_EINVAL, "checkpoints must be strictly ascending");
+    }
+    idx->stop.ncp = n;
+    for (int c = 0; c < 4; ++c) idx->stop.cps[c] = c < n ? hops[c] : 0;
+    idx->stop.hop = hops[0];
     return NSG_OK;
 }
 

@@ -42,6 +42,8 @@ struct StopModel {
     float *blob = nullptr;     // device, the kernel layout of the network form (see stop_decide)
     int kind = NSG_STOP_SCALAR;
     int in = 0, h = 0, hop = 0, grid_n = 0;
+    int ncp = 1;                 // decision checkpoints (cps[0] = hop)
+    int cps[4] = {0, 0, 0, 0};
     int enabled = 0;
     float calib_c = 1.0f;
 };

@@ -117,6 +117,7 @@ int launch_search(const SearchArgs &a) {
     p.budget = a.budget;
     p.learned = 0;
     p.s_hop = a.feature_hop > 0 ? a.feature_hop : 16;
+    p.s_cps = (uint64_t)(p.s_hop & 0xFFFF);
     if (a.learned) {
         const StopModel &sm = ix->stop;
         if (!sm.blob) return fail(NSG_ESTATE, "no early-stop model loaded");
@@ -127,6 +128,8 @@ int launch_search(const SearchArgs &a) {
         p.s_in = sm.in;
         p.s_kind = sm.kind;
         p.s_hop = sm.hop;
+        p.s_cps = 0;
+        for (int c = 0; c < sm.ncp; ++c) p.s_cps |= (uint64_t)(sm.cps[c] & 0xFFFF) << (16 * c);
         p.grid_n = sm.grid_n;
         p.calib_c = sm.calib_c;
     }

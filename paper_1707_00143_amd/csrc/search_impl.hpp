@@ -51,6 +51,7 @@ struct KParams {
     float *features;             // raw features [nq][kStopFeatures] after expansion s_hop, or NULL
     int s_in, s_hop, grid_n;
     int s_kind;                  // network form: NSG_STOP_SCALAR or NSG_STOP_QUERY
+    uint64_t s_cps;              // decision checkpoints, 16 bits each from the low end (first = s_hop), 0 ends
     float calib_c;
     int learned;                 // 1: queries with L >= 16 stop at their budget
 };
@@ -318,11 +319,14 @@ search_kernel(KParams p) {
         const int Lcur = Lq;
         // expansion budget: the caller's, and after the decision hop the
         // learned one (the search stops early, never later, than plain)
-        int64_t hcap = p.max_hops > 0 ? p.max_hops : INT64_MAX;
+        const int64_t base_cap = p.max_hops > 0 ? p.max_hops : INT64_MAX;
+        int64_t hcap = base_cap;
         // decision hop: features (if captured) and the learned budget
         const bool learn_q = STOP && p.learned && Lq >= 16;
         bool decide = STOP && (learn_q || p.features != nullptr);
         int Bq = 0;
+        int cpi = 0;                 // next decision checkpoint
+        int64_t cph = p.s_hop;       // its expansion count
 
         // query chunks in registers, aligned with the row chunks this lane reads
         float qv[CPL][EPC], sc[CPL][EPC];
@@ -438,21 +442,26 @@ search_kernel(KParams p) {
                 wave_sync();
             }
             vcount += cnt;
-            if (decide && hops >= p.s_hop) {
-                // after the decision hop: features of the state, the network,
-                // the budget (once per query)
-                decide = false;
+            if (decide && hops >= cph) {
+                // after a decision checkpoint: features of the state (captured
+                // at the first), the network, the budget; the latest decision
+                // replaces the budget, and the next checkpoint is taken only
+                // if the budget lets the search run past it
                 rp_store<NCH>(P, pool, lane);
                 wave_sync();
-                stop_decide(learn_q ? p.stop_plan : nullptr, p.s_kind, p.s_in, p.grid_n, p.calib_c, p.s_hop, pool,
-                            P.size, dstart, ne, hops, q, p.d, p.features ? p.features + qi * kStopFeatures : nullptr,
-                            lane, &Bq);
+                stop_decide(learn_q ? p.stop_plan : nullptr, p.s_kind, p.s_in, p.grid_n, p.calib_c, (int)cph, pool,
+                            P.size, dstart, ne, hops, q, p.d,
+                            p.features && cpi == 0 ? p.features + qi * kStopFeatures : nullptr, lane, &Bq);
                 Bq = __builtin_amdgcn_readfirstlane(Bq);
-                if (Bq > 0 && Bq < hcap) hcap = Bq;
+                if (learn_q) hcap = Bq > 0 && Bq < base_cap ? Bq : base_cap;
+                ++cpi;
+                const int64_t nxt = cpi < 4 ? (int64_t)((p.s_cps >> (16 * cpi)) & 0xFFFFu) : 0;
+                decide = learn_q && nxt > 0 && nxt < hcap;
+                cph = nxt;
                 wave_sync();
             }
         }
-        if (STOP && decide && p.features) {
+        if (STOP && cpi == 0 && p.features) {
             // ended before the decision hop: no features
             for (int t = lane; t < kStopFeatures; t += 64) p.features[qi * kStopFeatures + t] = NAN;
         }

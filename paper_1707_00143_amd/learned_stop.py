@@ -27,8 +27,8 @@ import dataclasses
 import numpy as np
 import torch
 
-from . import (STOP_FEATURES, STOP_QUERY, STOP_SCALAR, column_stats, load_stop_model, mlp_adam, mlp_forward, mlp_forward_backward, recall_hits,
-               search_batched, set_stop_mode)
+from . import (STOP_FEATURES, STOP_QUERY, STOP_SCALAR, column_stats, load_stop_model, mlp_adam, mlp_forward,
+               mlp_forward_backward, recall_hits, search_batched, set_stop_checkpoints, set_stop_mode)
 
 GRID = [int(round(16 * 2 ** (i / 4))) for i in range(25)]   # 16, 19, 23, ..., 1024 expansions
 HOP = 16
@@ -195,12 +195,49 @@ def calibrate(yhat, hits, grid, k=10, target=0.95, margin=0.0, hops=None, hop=HO
     return None
 
 
+def budget_checkpoints(yhats, valid, c, grid, cps, hops):
+    """Final budget per query with decisions at several checkpoints, as the
+    kernel takes them: at checkpoint j a query that reaches expansion cps[j]
+    (its unbudgeted search runs that far, valid[j]) and whose budget so far
+    exceeds cps[j] (always true at the first) gets max(cps[j], grid pick of
+    c * 2^yhats[j]) (no budget for a non-finite output).  inf = no budget."""
+    n = len(hops)
+    B = np.full(n, np.inf)
+    for j, (cp, yh, ok) in enumerate(zip(cps, yhats, valid)):
+        run = ok & (np.asarray(hops) >= cp)
+        if j > 0:
+            run &= B > cp
+        Bj = budget(yh, c, grid, cp)
+        B = np.where(run, np.where(np.isfinite(Bj), Bj, np.inf), B)
+    return B
+
+
+def calibrate_checkpoints(yhats, valid, hits, grid, cps, hops, k=10, target=0.95, margin=0.0):
+    """Smallest c on the 2^(1/16) ladder whose mean held-out recall meets
+    target + margin with decisions at every checkpoint.  Returns (c, recall,
+    mean budget, mean expansions) or None."""
+    h = np.asarray(hits)
+    g = np.asarray(grid)
+    hops = np.asarray(hops)
+    for j in range(-64, 129):
+        c = 2.0 ** (j / 16)
+        B = budget_checkpoints(yhats, valid, c, grid, cps, hops)
+        col = np.clip(np.searchsorted(g, np.where(np.isfinite(B), B, g[-1])), 0, len(g) - 1)
+        rec = h[np.arange(len(h)), col] / k
+        if rec.mean() >= target + margin:
+            used = np.minimum(np.where(np.isfinite(B), B, hops), hops)
+            return c, float(rec.mean()), float(np.where(np.isfinite(B), B, hops).mean()), float(used.mean())
+    return None
+
+
 def model_blob(P, mean, istd, grid):
     parts = [mean.cpu().numpy(), istd.cpu().numpy(), P.cpu().numpy(), np.asarray(grid, np.float32)]
     return np.concatenate([p.astype(np.float32).ravel() for p in parts]).tobytes()
 
 
-def install(index, P, mean, istd, c, grid=GRID, hop=HOP, kind=STOP_SCALAR):
+def install(index, P, mean, istd, c, grid=GRID, hop=HOP, kind=STOP_SCALAR, checkpoints=None):
     n_in = mean.numel()
     load_stop_model(index, model_blob(P, mean, istd, grid), n_in, HIDDEN, hop, len(grid), kind=kind)
+    if checkpoints:
+        set_stop_checkpoints(index, checkpoints)
     set_stop_mode(index, True, c)

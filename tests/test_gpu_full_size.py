@@ -315,3 +315,41 @@ def test_precision_workload_sampled_parity(gist, dt):
         r = compare(X, Q[s], ids[s], dist[s], rr_ids)
         assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
     ix.close()
+
+
+def test_precision_1M_sampled_parity():
+    """The 960-d workload at the configuration's full 1M rows in every storage
+    format, on a seeded random 70-regular graph (search parity does not need
+    a good graph): the walk equals the oracle's Algorithm 1 over the oracle's
+    decoded rows and the output the oracle's FP32 re-rank of its pool, on 64
+    sampled queries at L = 100."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_00143_amd as nsg
+    dev = torch.device("cuda:0")
+    w = datagen.GIST1M_LIKE
+    X = datagen.base(w)
+    Q = datagen.queries(w)[:64]
+    n = X.shape[0]
+    print(f"1M precision fixture: {w.name}, base {X.shape}", flush=True)
+    G = np.random.default_rng(2026).integers(0, n, size=(n, 70), dtype=np.uint32)
+    nav = int(np.random.default_rng(2027).integers(0, n))
+    Xd = torch.from_numpy(X).to(dev)
+    Gd = torch.from_numpy(G.view(np.int32)).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    k, L = 10, 100
+    for dt in ("f32", "bf16", "f16", "e4m3"):
+        ix = nsg.load_index(Xd, Gd, nav, dt)
+        walk_ids, walk_d = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(rerank=-1))
+        ids, dist = nsg.search(ix, Qd, k, L)
+        ix.close()
+        Xt = X if dt == "f32" else oracle.quantize(dt, X, oracle.scales(dt, X))[1]
+        o_ids, _, _, _, o_pids, _ = oracle.search(Xt, G, nav, Q, k, L, pool_stride=L, threads=16)
+        r = compare(Xt, Q, _np(walk_ids).view(np.uint32), _np(walk_d), o_ids)
+        assert r["ok"], (dt, {a: b for a, b in r.items() if a != "bad"})
+        if dt != "f32":
+            rr_ids, _ = oracle.rerank(X, Q, o_pids, k)
+            r = compare(X, Q, _np(ids).view(np.uint32), _np(dist), rr_ids)
+            assert r["ok"], (dt, {a: b for a, b in r.items() if a != "bad"})
+        print(f"1M precision parity: {dt} ok", flush=True)
+        del Xt

@@ -289,6 +289,78 @@ def test_query_form_learned_stop_matches_oracle(nsg, tiny_index, dt, L, hop):
     ix.close()
 
 
+@pytest.mark.parametrize("dt,L,cps", [("f16", 60, (16, 32, 64)), ("f32", 120, (16, 24, 40, 72))])
+def test_query_form_checkpoints_match_oracle(nsg, tiny_index, dt, L, cps):
+    """Decisions at several checkpoints: at every checkpoint a query still
+    allowed to run past it takes the budget the network gives for its state
+    there (the expansion count input differs between checkpoints); the final
+    budget equals the oracle's replay of those decisions (its FP16-inference
+    network on its own search states), and the walk with it equals the
+    oracle's Algorithm 1."""
+    dev = _dev()
+    import math
+    from paper_1707_00143_amd import learned_stop as ls
+    X, G, nav, Q = tiny_index["X"], tiny_index["graph"], tiny_index["nav"], tiny_index["Q"]
+    ix = nsg.load_index(torch.from_numpy(X).to(dev), torch.from_numpy(G.view(np.int32)).to(dev), nav, dt)
+    Qd = torch.from_numpy(Q).to(dev)
+    nq, k, H = len(Q), 10, ls.HIDDEN
+    hp = torch.zeros(nq, dtype=torch.int64, device=dev)
+    nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(hops=hp))
+    rows = []
+    for cp in cps:
+        f = torch.empty((nq, nsg.STOP_FEATURES), dtype=torch.float32, device=dev)
+        nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(features=f, feature_hop=cp, max_hops=cp))
+        rows.append(ls.query_inputs(Qd, f, cp))
+    Xin = torch.cat(rows)
+    n_in = Xin.shape[1]
+    keep = ~torch.isnan(Xin).any(1)
+    mean, istd = nsg.column_stats(Xin[keep].contiguous())
+    m32, s32 = _np(mean), _np(istd)
+    P = ls.init_params(n_in, H, 13).astype(np.float64)
+    y = oracle.mlp_forward_fp16(P, (_np(Xin[keep]) - m32) * s32, n_in, H)
+    sd = float(y.std()) or 1.0
+    P[-(H + 1):-1] *= 1.5 / sd
+    P[-1] = (P[-1] - float(y.mean())) * 1.5 / sd + math.log2(float(hp.float().mean().item()))
+    P = P.astype(np.float32)
+    ls.install(ix, torch.from_numpy(P).to(dev), mean, istd, 1.0, hop=cps[0], kind=nsg.STOP_QUERY,
+               checkpoints=list(cps))
+    with pytest.raises(nsg.NSGError):
+        nsg.set_stop_checkpoints(ix, [32, 16])           # not ascending
+    Bu = torch.zeros(nq, dtype=torch.int32, device=dev)
+    ids, dist = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(learned_stop=1, budget=Bu))
+    wi, wd = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(learned_stop=1, rerank=-1))
+    Bu = _np(Bu)
+    Xt = X if dt == "f32" else oracle.quantize(dt, X, oracle.scales(dt, X))[1]
+    states = [oracle.search(Xt, G, nav, Q, k, L, pool_stride=L, max_hops=cp) for cp in cps]
+    P64 = P.astype(np.float64)
+    ties, later = 0, 0
+    for i in range(nq):
+        B, near = None, False
+        for j, cp in enumerate(cps):
+            _, _, oh, _, opids, opd = states[j]
+            if oh[i] < cp or (j > 0 and B is not None and B <= cp):
+                break
+            v = opids[i] != oracle.SENT
+            zi = (oracle.stop_query_inputs(Q[i], opd[i][v], cp).astype(np.float32) - m32) * s32
+            t = 2.0 ** float(oracle.mlp_forward_fp16(P64, zi, n_in, H)[0])
+            near |= min(abs(t / g - 1.0) for g in ls.GRID) < 5e-3
+            B = _grid_pick(t, ls.GRID, cp)
+            later += j > 0
+        want = 0 if B is None else B
+        if Bu[i] != want:
+            assert near, (i, int(Bu[i]), want)
+            ties += 1
+    assert ties <= max(1, nq // 50), ties
+    assert later > 0                                     # some queries were decided again
+    o_ids, _, o_hops, _, o_pids, _ = oracle.search(Xt, G, nav, Q, k, L, pool_stride=L, max_hops=Bu)
+    r = compare(Xt, Q, _np(wi).view(np.uint32), _np(wd), o_ids)
+    assert r["ok"], (dt, L, {a: b for a, b in r.items() if a != "bad"}, r["bad"][:3])
+    rr_ids = o_ids if dt == "f32" else oracle.rerank(X, Q, o_pids, k)[0]
+    r = compare(X, Q, _np(ids).view(np.uint32), _np(dist), rr_ids)
+    assert r["ok"], (dt, L, {a: b for a, b in r.items() if a != "bad"}, r["bad"][:3])
+    ix.close()
+
+
 def test_max_hops_matches_oracle(nsg, tiny_index):
     """A caller-given expansion budget equals the oracle's Algorithm 1 stopped
     after that many expansions (FP32, several budgets in one batch)."""
