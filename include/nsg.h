@@ -142,7 +142,7 @@ typedef struct nsg_search_opts {
     uint32_t *pool_ids;      /* device [nq][pool_stride] final pool ids, or NULL */
     float *pool_dist;        /* device [nq][pool_stride] final pool distances */
     int32_t pool_stride;
-    int32_t feature_hop;     /* hop at which `features` are taken (0: 16; the model's hop when learned) */
+    int32_t feature_hop;     /* hop at which `features` are taken (0: 16; at most 65535; the model's hop when learned) */
     int64_t *nedges;         /* device [nq] valid neighbour entries read over all expansions, or NULL */
     int32_t lanes_per_row;   /* lanes that gather one row (8, 16, 32, 64); 0: default */
     uint32_t *counter;       /* device scratch word for the persistent work counter (reset by the

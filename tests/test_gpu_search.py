@@ -275,3 +275,24 @@ def test_large_pools_launch_invariant(tiny_gpu, nsg, L):
             else:
                 same = torch.equal(ids, ref[0]) and torch.equal(dist, ref[1])
                 assert same, (L, lpr, {a: b for a, b in o.items() if not isinstance(b, torch.Tensor)})
+
+
+def test_persistent_batches_on_two_streams(tiny_gpu, nsg):
+    """Persistent-grid batches issued on two streams at once (each stream has
+    its own work counter; the calls bring none) all equal the result of one
+    call on the default stream."""
+    t = tiny_gpu
+    nq = 100
+    Q = t["Qd"][:nq].contiguous()
+    ref = nsg.search_batched(t["ix"], Q, k_scalar=10, L_scalar=60, opts=dict(persistent=1))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for rep in range(3):
+        for s in streams:
+            with torch.cuda.stream(s):
+                outs.append(nsg.search_batched(t["ix"], Q, k_scalar=10, L_scalar=60, opts=dict(persistent=1),
+                                               stream=s))
+    torch.cuda.synchronize()
+    for ids, dist in outs:
+        assert torch.equal(ids, ref[0]) and torch.equal(dist, ref[1])
