@@ -296,3 +296,35 @@ def test_persistent_batches_on_two_streams(tiny_gpu, nsg):
     torch.cuda.synchronize()
     for ids, dist in outs:
         assert torch.equal(ids, ref[0]) and torch.equal(dist, ref[1])
+
+
+@pytest.mark.parametrize("d,R", [(1024, 128), (1, 8), (37, 128), (129, 65)])
+def test_extreme_shapes_match_oracle(nsg, d, R):
+    """The largest dimension and out-degree the library accepts (d = 1024,
+    R = 128: a neighbour row spans two 64-lane loads), the smallest dimension,
+    and ragged ones, in every storage format, on a seeded random R-regular
+    graph: the walk equals the oracle's Algorithm 1 over the decoded rows and
+    the re-ranked output the oracle's FP32 re-rank of its pool."""
+    dev = _dev()
+    rng = np.random.default_rng(d * 1000 + R)
+    n, nq, k, L = 3000, 24, 10, 64
+    X = (rng.normal(size=(n, d)) * 3 + 1).astype(np.float32)
+    Q = (rng.normal(size=(nq, d)) * 3 + 1).astype(np.float32)
+    G = rng.integers(0, n, size=(n, R), dtype=np.uint32)
+    G[::7, R // 2:] = 0xFFFFFFFF                       # some short rows (sentinel tails)
+    nav = 11
+    Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
+    Gd = torch.from_numpy(G.view(np.int32)).to(dev)
+    for dt in ("f32", "bf16", "f16", "e4m3"):
+        ix = nsg.load_index(Xd, Gd, nav, dt)
+        wi, wd = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(rerank=-1))
+        ids, dist = nsg.search(ix, Qd, k, L)
+        ix.close()
+        Xt = X if dt == "f32" else oracle.quantize(dt, X, oracle.scales(dt, X))[1]
+        o_ids, _, _, _, o_pids, _ = oracle.search(Xt, G, nav, Q, k, L, pool_stride=L)
+        r = compare(Xt, Q, _np(wi).view(np.uint32), _np(wd), o_ids)
+        assert r["ok"], (d, R, dt, {a: b for a, b in r.items() if a != "bad"})
+        if dt != "f32":
+            rr_ids, _ = oracle.rerank(X, Q, o_pids, k)
+            r = compare(X, Q, _np(ids).view(np.uint32), _np(dist), rr_ids)
+            assert r["ok"], (d, R, dt, {a: b for a, b in r.items() if a != "bad"})
