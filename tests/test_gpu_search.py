@@ -322,9 +322,25 @@ def test_extreme_shapes_match_oracle(nsg, d, R):
         ix.close()
         Xt = X if dt == "f32" else oracle.quantize(dt, X, oracle.scales(dt, X))[1]
         o_ids, _, _, _, o_pids, _ = oracle.search(Xt, G, nav, Q, k, L, pool_stride=L)
-        r = compare(Xt, Q, _np(wi).view(np.uint32), _np(wd), o_ids)
+        wids = _np(wi).view(np.uint32)
+        r = compare(Xt, Q, wids, _np(wd), o_ids, rtol=1e-5 if dt == "f32" else 1.0)
         assert r["ok"], (d, R, dt, {a: b for a, b in r.items() if a != "bad"})
         if dt != "f32":
+            # the walk forms q_j - s_j * code_j with one rounding (a fused
+            # decode), the decoded rows round s_j * code_j first: per
+            # dimension the two differ by at most |x_j| * 2^-24, so the
+            # squared distance by at most 2 sum_j |q_j - x_j| |x_j| 2^-24
+            # (plus the FP32 sum's own rounding, 1e-5 relative)
+            Q64, X64 = Q.astype(np.float64), Xt.astype(np.float64)
+            wdist = _np(wd)
+            for i in range(nq):
+                for j, u in enumerate(wids[i]):
+                    if u == 0xFFFFFFFF:
+                        continue
+                    t = Q64[i] - X64[u]
+                    ref = float((t * t).sum())
+                    bound = 1e-5 * ref + 2.0 * float((np.abs(t) * np.abs(X64[u])).sum()) * 2.0 ** -24 * 1.01
+                    assert abs(float(wdist[i, j]) - ref) <= bound, (d, R, dt, i, j, float(wdist[i, j]), ref, bound)
             rr_ids, _ = oracle.rerank(X, Q, o_pids, k)
             r = compare(X, Q, _np(ids).view(np.uint32), _np(dist), rr_ids)
             assert r["ok"], (d, R, dt, {a: b for a, b in r.items() if a != "bad"})
