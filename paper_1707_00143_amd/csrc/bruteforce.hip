@@ -1,24 +1,25 @@
 // Exact kNN by brute force (serial scan) on gfx950 matrix cores.
 //
-// Stage 1 (matrix cores): a block owns 64 queries and one contiguous split of
-// the base.  For each tile of 64 base rows, the 64x64 block of inner products
-// of centred vectors (q - mu).(x - mu) is accumulated with FP32
-// v_mfma_f32_16x16x4f32 (each of the 4 waves: 16 queries x 64 rows), turned
-// into approximate squared distances |q-mu|^2 + |x-mu|^2 - 2 (q-mu).(x-mu),
-// and every value below the query's current threshold is appended to that
-// query's candidate buffer (device memory: appends are rare once the
-// threshold is tight, and LDS then holds only the staged base chunk, the
-// thresholds and a sort scratch per wave, so several blocks share a CU).  A
-// buffer that could overflow on the next tile is sorted (in the wave's LDS
-// scratch) and cut back to its Kp best, which tightens the threshold (the
-// buffer holds Kp + 2 tiles, so sorts are rare once the threshold is tight).
-// With d <= 128 each wave keeps its 16 centred queries as matrix-core
-// operands in registers for the whole scan and only base rows are staged.
-// Each block writes Kp candidates per query for its split.
+// Stage 1 (matrix cores): a block owns a tile of queries and one contiguous
+// split of the base.  For each tile of 64 base rows the inner products of
+// centred vectors (q - mu).(x - mu) are accumulated with FP32
+// v_mfma_f32_16x16x4f32, turned into rank values, and every value below the
+// query's current threshold is appended to that query's candidate buffer
+// (device memory: appends are rare once the threshold is tight).  A buffer
+// that could overflow on the next tile is sorted (in the wave's LDS scratch)
+// and cut back to its Kp best, which tightens the threshold (the buffer
+// holds Kp + 2 tiles, so sorts are rare once the threshold is tight).  Each
+// block writes Kp candidates per query for its split.
+//  * d <= 128 (bf_wide_kernel): 4 waves x 32 queries per block; each wave
+//    keeps its centred queries as matrix-core operands in registers for the
+//    whole scan, owns all 64 rows of a tile and appends and compacts only its
+//    own queries; the base tile is staged once per block, double buffered.
+//  * d > 128 (bf_tile_kernel): 4 waves x 16 queries per block; 32-dim chunks
+//    of queries and base rows are staged through LDS.
 // Stage 2: per query (one wave), exact FP32 squared distances sum (q_j-x_j)^2
 // of all candidates of all splits, bitonic sort by (distance, id), first k.
 // Centring keeps the cancellation error of the inner-product form small;
-// the over-fetch margin (Kp >= k + 32) absorbs the rest before the exact pass.
+// the over-fetch margin (Kp >= k + 24) absorbs the rest before the exact pass.
 #include "common.hpp"
 
 #include <algorithm>
@@ -39,6 +40,7 @@ struct BFParams {
     int64_t split_len;
     int nsplit;
     int exclude_self;
+    int vec4;              // rows 16-byte aligned (d % 4 == 0, aligned base): vector loads
     uint32_t *cand_ids;    // [nq][nsplit][Kp]
     uint64_t *cand_buf;    // [qtiles][nsplit][BQ][cap] candidate buffers
 };
@@ -129,12 +131,13 @@ __device__ inline void wave_sort_buf(uint64_t *buf, int cnt, int cap, int lane) 
         }
 }
 
-template <bool AREG>
+// Stage 1 for d > 128: a block owns 64 queries (16 per wave), and each
+// 32-dim chunk of the queries and of a 64-row base tile is staged through LDS.
 __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     float *Xs = reinterpret_cast<float *>(smem);               // [KB][KPAD]
-    float *Qs = Xs + KB * KPAD;                                 // [KB][KPAD] (d > 128 only)
-    float *thr = Qs + (AREG ? 0 : KB * KPAD);                   // [BQ]
+    float *Qs = Xs + KB * KPAD;                                 // [KB][KPAD]
+    float *thr = Qs + KB * KPAD;                                // [BQ]
     int *cnt = reinterpret_cast<int *>(thr + BQ);               // [BQ]
     uint64_t *scratch = reinterpret_cast<uint64_t *>(cnt + BQ); // [4][cap]: one sort buffer per wave
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -147,16 +150,6 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
     if (tid < BQ) { thr[tid] = INFINITY; cnt[tid] = 0; }
     bsync();
     const int rq = lane & 15, kq = lane >> 4;   // MFMA operand row / k group of this lane
-    // centred query operands of this wave (AREG: d <= 128, k-step s uses a[s])
-    float a_reg[AREG ? 32 : 1];
-    if (AREG) {
-        const int64_t qi = q0 + 16 * w + rq;
-#pragma unroll
-        for (int s4 = 0; s4 < (AREG ? 32 : 1); ++s4) {
-            const int j = 4 * s4 + kq;
-            a_reg[s4] = (qi < p.nq && j < p.d) ? p.queries[qi * p.d + j] - p.mu[j] : 0.0f;
-        }
-    }
     // |q - mu|^2 of the 4 query rows this lane's accumulators hold
     float qn[4];
 #pragma unroll
@@ -164,65 +157,33 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
         const int64_t qi = q0 + 16 * w + 4 * kq + i;
         qn[i] = qi < p.nq ? p.qnorm[qi] : 0.0f;
     }
-    // base chunk (64 rows x 32 dims) of the next step, loaded into registers
-    // while the matrix cores work on the current one (AREG path)
-    float xr[(BX * KB) / 256];
-    const int kk_t = tid % KB;   // the dimension offset this thread stages (fixed: 256 % KB == 0)
-    auto load_chunk = [&](int64_t cx0, int ck0) {
-#pragma unroll
-        for (int it = 0; it < (BX * KB) / 256; ++it) {
-            const int r = (tid + it * 256) / KB;
-            const int j = ck0 + kk_t;
-            const int64_t xi = cx0 + r;
-            xr[it] = (xi < xe && j < p.d) ? p.base[xi * p.d + j] : 0.0f;
-        }
-    };
-    if (AREG) load_chunk(xb, 0);
     for (int64_t x0 = xb; x0 < xe; x0 += BX) {
         f32x4 acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = 0; k0 < p.d; k0 += KB) {
+            // stage centred Q and X chunks, k-major: 64 rows x 32 dims each
 #pragma unroll
-        for (int k0 = 0; k0 < (AREG ? 128 : 65536); k0 += KB) {
-            if (k0 >= p.d) break;   // AREG: a constant trip count keeps a_reg in registers
-            if (AREG) {
-                // stage the prefetched chunk, centred, k-major; then prefetch the next
-                bsync();
-                const int j = k0 + kk_t;
-                const float mj = j < p.d ? p.mu[j] : 0.0f;
-#pragma unroll
-                for (int it = 0; it < (BX * KB) / 256; ++it) {
-                    const int r = (tid + it * 256) / KB;
-                    Xs[kk_t * KPAD + r] = (x0 + r < xe && j < p.d) ? xr[it] - mj : 0.0f;
-                }
-                bsync();
-                const bool more_k = k0 + KB < p.d;
-                const int64_t nx0 = more_k ? x0 : x0 + BX;
-                if (nx0 < xe) load_chunk(nx0, more_k ? k0 + KB : 0);
-            } else {
-                // stage centred Q and X chunks, k-major: 64 rows x 32 dims each
-#pragma unroll
-                for (int it = 0; it < (BQ * KB) / 256; ++it) {
-                    int e = tid + it * 256;
-                    int r = e / KB, kk = e % KB;
-                    int j = k0 + kk;
-                    int64_t qi = q0 + r, xi = x0 + r;
-                    float mj = j < p.d ? p.mu[j] : 0.0f;
-                    Qs[kk * KPAD + r] = (qi < p.nq && j < p.d) ? p.queries[qi * p.d + j] - mj : 0.0f;
-                    Xs[kk * KPAD + r] = (xi < xe && j < p.d) ? p.base[xi * p.d + j] - mj : 0.0f;
-                }
-                bsync();
+            for (int it = 0; it < (BQ * KB) / 256; ++it) {
+                int e = tid + it * 256;
+                int r = e / KB, kk = e % KB;
+                int j = k0 + kk;
+                int64_t qi = q0 + r, xi = x0 + r;
+                float mj = j < p.d ? p.mu[j] : 0.0f;
+                Qs[kk * KPAD + r] = (qi < p.nq && j < p.d) ? p.queries[qi * p.d + j] - mj : 0.0f;
+                Xs[kk * KPAD + r] = (xi < xe && j < p.d) ? p.base[xi * p.d + j] - mj : 0.0f;
             }
+            bsync();
 #pragma unroll
             for (int kk = 0; kk < KB; kk += 4) {
-                float a = AREG ? a_reg[((k0 + kk) >> 2) & 31] : Qs[(kk + kq) * KPAD + 16 * w + rq];
+                float a = Qs[(kk + kq) * KPAD + 16 * w + rq];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     float b = Xs[(kk + kq) * KPAD + 16 * t + rq];
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
                 }
             }
-            if (!AREG) bsync();
+            bsync();
         }
         // epilogue: lane holds rows 4*kq + i of this wave's 16 queries, column rq of tile t
 #pragma unroll
@@ -273,6 +234,255 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
     }
 }
 
+// Order-preserving map of a float to 32 bits (ascending keys = ascending
+// values, negative values included).
+__device__ inline uint32_t ord_bits(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float ord_float(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__device__ inline void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Stage 1 for d <= 128 with wide query tiles.  Every wave owns QW queries
+// (QW / 16 matrix-core row groups whose centred operands stay in registers
+// for the whole scan) and all 64 rows of each base tile.  The block stages a
+// tile once in LDS for its 4 waves (double buffered, one barrier per tile;
+// the next tile is loaded into registers while the current one is
+// multiplied), so the base is streamed once per 4 * QW queries.  Inside the
+// inner product the dimensions are permuted (any permutation applied to
+// both operands gives the same sum): lane group kq takes dims [kq*S, kq*S+S)
+// over the S k-steps, so one 16-byte LDS read supplies four k-steps.
+// Rank value a = |x - mu|^2 - 2 (q - mu).(x - mu), which is the squared
+// distance minus |q - mu|^2 and so orders a query's rows as the distance
+// does.  Each wave appends its own queries' values below their thresholds
+// and compacts its own buffers: appends and compaction need no block-wide
+// synchronisation.  Values of rows past the split carry |x - mu|^2 = +inf
+// and never pass; queries past nq get threshold -inf.
+template <int DP, int QW, bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) bf_wide_kernel(BFParams p) {
+    constexpr int S = DP / 4;            // k-steps of 4 dims
+    constexpr int G = QW / 16;           // row groups per wave
+    constexpr int LD = DP + 4;           // staged row stride (floats)
+    constexpr int F4 = DP / 4;           // 16-byte pieces per staged row
+    constexpr int NIT = BX * F4 / 256;   // pieces per thread per tile
+    static_assert(DP % 16 == 0 && DP <= 128 && (BX * F4) % 256 == 0, "tile shape");
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *Xs = reinterpret_cast<float *>(smem);                          // [2][BX][LD]
+    float *mus = Xs + 2 * BX * LD;                                        // [DP] centre, 0 past d
+    float *thr_s = mus + DP;                                              // [4][QW]
+    int *cnt_s = reinterpret_cast<int *>(thr_s + 4 * QW);                 // [4][QW]
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(cnt_s + 4 * QW);     // [4][cap]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int rq = lane & 15, kq = lane >> 4;
+    const int64_t qb = (int64_t)blockIdx.x * 4 * QW;   // first query of the block
+    const int64_t qw0 = qb + (int64_t)w * QW;           // first query of the wave
+    const int split = blockIdx.y;
+    const int64_t xb = (int64_t)split * p.split_len;
+    const int64_t xe = std::min<int64_t>(p.n, xb + p.split_len);
+    uint64_t *buf = p.cand_buf + ((int64_t)blockIdx.x * p.nsplit + split) * (int64_t)(4 * QW) * p.cap +
+                    (int64_t)w * QW * p.cap;
+    float *thr_w = thr_s + w * QW;
+    int *cnt_w = cnt_s + w * QW;
+    uint64_t *sw = scratch + (size_t)w * p.cap;
+    for (int j = tid; j < DP; j += 256) mus[j] = j < p.d ? p.mu[j] : 0.0f;
+    if (lane < QW) {
+        thr_w[lane] = qw0 + lane < p.nq ? INFINITY : -INFINITY;
+        cnt_w[lane] = 0;
+    }
+    // centred query operands: a[g][s] = q[qw0 + 16 g + rq][kq * S + s] - mu
+    float a[G][S];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t qi = qw0 + 16 * g + rq;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int j = kq * S + s;
+            a[g][s] = (qi < p.nq && j < p.d) ? p.queries[qi * p.d + j] - p.mu[j] : 0.0f;
+        }
+    }
+    // base tile pieces of this thread: piece f = tid + 256 it is row f / F4,
+    // dims 4 (f % F4) .. + 3; the next tile is loaded in two halves (the
+    // first while the first half of the k-steps runs, the second while the
+    // rest runs).  Loads use clamped in-range addresses and a select (no
+    // branches); rows past the split and dims past d give 0.
+    constexpr int H = NIT / 2;
+    float4 xr[H];
+    auto load_half = [&](int64_t x0, int h) {
+        const float *tb = p.base + x0 * p.d;
+        const int rows = (int)std::min<int64_t>(BX, xe - x0);
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+            const int f = tid + 256 * (h * H + u);
+            const int r = f / F4, j = 4 * (f % F4);
+            const int rr = std::min(r, rows - 1);
+            if (VEC) {
+                const float4 v = *reinterpret_cast<const float4 *>(tb + (uint32_t)(rr * p.d + std::min(j, p.d - 4)));
+                const bool ok = r < rows && j < p.d;
+                xr[u] = ok ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            } else {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float w4 = tb[(uint32_t)(rr * p.d + std::min(j + e, p.d - 1))];
+                    v[e] = r < rows && j + e < p.d ? w4 : 0.0f;
+                }
+                xr[u] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+    };
+    auto store_half = [&](float *dst, int h) {
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+            const int f = tid + 256 * (h * H + u);
+            const int r = f / F4, j = 4 * (f % F4);
+            const float4 m = *reinterpret_cast<const float4 *>(mus + j);
+            float4 v = xr[u];
+            v.x -= m.x; v.y -= m.y; v.z -= m.z; v.w -= m.w;
+            *reinterpret_cast<float4 *>(dst + r * LD + j) = v;
+        }
+    };
+    auto load_xn = [&](int64_t x0, float *xn) {
+        const int rows = (int)std::min<int64_t>(BX, xe - x0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int r = 16 * t + rq;
+            const float u = p.xnorm[x0 + std::min(r, rows - 1)];
+            xn[t] = r < rows ? u : INFINITY;
+        }
+    };
+    bsync();   // centre and counters visible
+    float thr[G][4];
+    auto load_thr = [&]() {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) thr[g][i] = thr_w[16 * g + 4 * kq + i];
+    };
+    load_thr();
+    if (xb < xe) {
+        load_half(xb, 0);
+        store_half(Xs, 0);
+        load_half(xb, 1);
+        store_half(Xs, 1);
+    }
+    bsync();
+    int cur = 0;
+    for (int64_t x0 = xb; x0 < xe; x0 += BX) {
+        const bool more = x0 + BX < xe;
+        float xn[4];
+        load_xn(x0, xn);
+        if (more) load_half(x0 + BX, 0);
+        const float *Xc = Xs + cur * BX * LD;
+        float *Xn = Xs + (cur ^ 1) * BX * LD;
+        f32x4 acc[G][4];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[g][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s4 = 0; s4 < S; s4 += 4) {
+            if (s4 == S / 2 && more) {
+                store_half(Xn, 0);
+                load_half(x0 + BX, 1);
+            }
+            float4 b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[t] = *reinterpret_cast<const float4 *>(Xc + (16 * t + rq) * LD + kq * S + s4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float bv = e == 0 ? b[t].x : e == 1 ? b[t].y : e == 2 ? b[t].z : b[t].w;
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g][s4 + e], bv, acc[g][t], 0, 0, 0);
+                }
+        }
+        // epilogue: lane holds queries 16 g + 4 kq + i of the wave, row 16 t + rq
+        // of the tile; rank values in place, a query's own row made +inf in
+        // the one tile that can hold it (exclude_self)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[g][t][i] = fmaf(-2.0f, acc[g][t][i], xn[t]);
+        if (p.exclude_self && x0 < qw0 + QW && qw0 < x0 + BX) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (x0 + 16 * t + rq == qw0 + 16 * g + 4 * kq + i) acc[g][t][i] = INFINITY;
+        }
+        // per query row: the lane's 4 values are tested one by one only when
+        // their minimum passes (rare once the threshold is tight)
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float m = fminf(fminf(acc[g][0][i], acc[g][1][i]), fminf(acc[g][2][i], acc[g][3][i]));
+                if (m < thr[g][i]) {
+                    const int r = 16 * g + 4 * kq + i;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float v = acc[g][t][i];
+                        if (v < thr[g][i]) {
+                            const int slot = atomicAdd(&cnt_w[r], 1);
+                            buf[(size_t)r * p.cap + slot] =
+                                ((uint64_t)ord_bits(v) << 32) | (uint32_t)(x0 + 16 * t + rq);
+                        }
+                    }
+                }
+            }
+        wave_fence();
+        // compaction of this wave's buffers that could overflow on the next tile
+        uint64_t full = __builtin_amdgcn_ballot_w64(lane < QW && cnt_w[lane < QW ? lane : 0] > p.cap - BX);
+        if (full) {
+            while (full) {
+                const int r = __builtin_ctzll(full);
+                full &= full - 1;
+                const int c = cnt_w[r];
+                uint64_t *br = buf + (size_t)r * p.cap;
+                for (int j = lane; j < c; j += 64) sw[j] = br[j];
+                wave_sort_buf(sw, c, p.cap, lane);
+                for (int j = lane; j < p.Kp; j += 64) br[j] = sw[j];
+                const float tnew = ord_float((uint32_t)(sw[p.Kp - 1] >> 32));
+                wave_fence();
+                if (lane == 0) {
+                    cnt_w[r] = p.Kp;
+                    thr_w[r] = tnew;
+                }
+                wave_fence();
+            }
+            load_thr();
+        }
+        if (more) store_half(Xn, 1);
+        cur ^= 1;
+        bsync();
+    }
+    // final: sort each buffer of the wave, write Kp candidates (sentinel padded)
+    for (int r = 0; r < QW; ++r) {
+        const int64_t qi = qw0 + r;
+        if (qi >= p.nq) break;
+        const int c = cnt_w[r];
+        const uint64_t *br = buf + (size_t)r * p.cap;
+        for (int j = lane; j < c; j += 64) sw[j] = br[j];
+        wave_sort_buf(sw, c, p.cap, lane);
+        uint32_t *dst = p.cand_ids + (qi * p.nsplit + split) * (int64_t)p.Kp;
+        for (int j = lane; j < p.Kp; j += 64) dst[j] = j < c ? (uint32_t)(sw[j] & 0xFFFFFFFFu) : NSG_SENT;
+        wave_fence();
+    }
+}
+
 // one wave per query: exact distances of all candidates, sort, first k
 __global__ void __launch_bounds__(256) bf_rerank_kernel(const float *base, const float *queries, int64_t nq,
                                                         int d, const uint32_t *cand, int ncand, int k,
@@ -310,6 +520,8 @@ __global__ void __launch_bounds__(256) bf_rerank_kernel(const float *base, const
 
 int mean_blocks(int64_t n) { return (int)std::min<int64_t>(n, 1024); }
 
+constexpr int kWideQW = 32;   // queries per wave of the wide stage 1
+
 int launch_mean(const float *x, int64_t n, int d, float *mu, float2 *part, hipStream_t st) {
     const int nblk = mean_blocks(n);
     hipLaunchKernelGGL(colsum_part_kernel, dim3((unsigned)nblk), dim3(d < 256 ? (d + 63) / 64 * 64 : 256), 0, st,
@@ -318,6 +530,27 @@ int launch_mean(const float *x, int64_t n, int d, float *mu, float2 *part, hipSt
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(NSG_EDEVICE, "mean kernels failed: %s", hipGetErrorString(e));
     return NSG_OK;
+}
+
+// the wide stage-1 kernel for rows padded to DP dims, and its LDS bytes
+struct WideKernel {
+    const void *fn;
+    size_t lds;
+};
+
+template <int DP, bool VEC>
+WideKernel wide_kernel_t(int cap) {
+    return {(const void *)bf_wide_kernel<DP, kWideQW, VEC>,
+            (size_t)2 * BX * (DP + 4) * 4 + (size_t)DP * 4 + (size_t)4 * kWideQW * 8 + (size_t)4 * cap * 8};
+}
+
+template <bool VEC>
+WideKernel wide_kernel_v(int d, int cap) {
+    const int DP = (d + 31) / 32 * 32;
+    return DP == 32 ? wide_kernel_t<32, VEC>(cap)
+           : DP == 64 ? wide_kernel_t<64, VEC>(cap)
+           : DP == 96 ? wide_kernel_t<96, VEC>(cap)
+                      : wide_kernel_t<128, VEC>(cap);
 }
 
 }  // namespace nsg
@@ -341,9 +574,31 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     const int Kp = (k + 24 + 31) / 32 * 32;
     int cap = 1;
     while (cap < Kp + 2 * BX) cap <<= 1;
-    // splits: enough blocks to fill the machine, at least a few tiles each
-    int64_t qtiles = (nq + BQ - 1) / BQ;
-    int64_t want = std::max<int64_t>(1, 2048 / std::max<int64_t>(qtiles, 1));
+    // d <= 128: wide query tiles (4 waves x kWideQW queries per block)
+    const bool wide = d <= 128;
+    const bool vec4 = d % 4 == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0;
+    const int bq = wide ? 4 * kWideQW : BQ;
+    const int64_t qtiles = (nq + bq - 1) / bq;
+    // splits of the base: with fewer query tiles than resident blocks, enough
+    // splits for one full round of blocks (fewer splits keep the exact pass
+    // short); at least a few tiles per split
+    int64_t want;
+    WideKernel wk{};
+    const size_t tile_lds = (size_t)2 * KB * KPAD * 4 + BQ * 8 + (size_t)4 * cap * 8;
+    if (wide) {
+        wk = vec4 ? wide_kernel_v<true>(d, cap) : wide_kernel_v<false>(d, cap);
+        NSG_HIP(hipFuncSetAttribute(wk.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wk.lds));
+        int dev = 0, cus = 0, per_cu = 0;
+        NSG_HIP(hipGetDevice(&dev));
+        NSG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        NSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wk.fn, 256, wk.lds));
+        const int64_t slots = std::max<int64_t>(1, (int64_t)cus * per_cu);
+        want = std::max<int64_t>(1, slots / qtiles);
+    } else {
+        NSG_HIP(hipFuncSetAttribute((const void *)bf_tile_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)tile_lds));
+        want = std::max<int64_t>(1, 2048 / qtiles);
+    }
     int64_t max_split = std::max<int64_t>(1, n / (BX * 8));
     int nsplit = (int)std::min<int64_t>(std::min<int64_t>(want, max_split), std::max(1, 4096 / Kp));
     int64_t split_len = (n + nsplit - 1) / nsplit;
@@ -362,10 +617,11 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     NSG_HIP(hipMallocAsync((void **)&xnorm, sizeof(float) * n, st));
     NSG_HIP(hipMallocAsync((void **)&qnorm, sizeof(float) * nq, st));
     NSG_HIP(hipMallocAsync((void **)&cand, sizeof(uint32_t) * nq * ncand, st));
-    NSG_HIP(hipMallocAsync((void **)&cbuf, sizeof(uint64_t) * qtiles * nsplit * BQ * cap, st));
+    NSG_HIP(hipMallocAsync((void **)&cbuf, sizeof(uint64_t) * qtiles * nsplit * bq * cap, st));
     if (int rc = launch_mean(base, n, d, mu, acc, st)) return rc;
     hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, d, mu, xnorm);
-    hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, queries, nq, d, mu, qnorm);
+    if (!wide)   // the wide kernel ranks by |x - mu|^2 - 2 (q - mu).(x - mu): no query norms
+        hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, queries, nq, d, mu, qnorm);
     BFParams p{};
     p.base = base;
     p.queries = queries;
@@ -382,20 +638,24 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     p.exclude_self = exclude_self ? 1 : 0;
     p.cand_ids = cand;
     p.cand_buf = cbuf;
-    const size_t lds = (size_t)(d <= 128 ? 1 : 2) * KB * KPAD * 4 + BQ * 8 + (size_t)4 * cap * 8;
-    if (d <= 128) {
-        NSG_HIP(hipFuncSetAttribute((const void *)bf_tile_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
-        hipLaunchKernelGGL(bf_tile_kernel<true>, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), lds, st, p);
+    p.vec4 = vec4 ? 1 : 0;
+    hipError_t le;
+    if (wide) {
+        void *args[] = {&p};
+        le = hipLaunchKernel(wk.fn, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), args, wk.lds, st);
     } else {
-        NSG_HIP(hipFuncSetAttribute((const void *)bf_tile_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
-        hipLaunchKernelGGL(bf_tile_kernel<false>, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), lds, st, p);
+        hipLaunchKernelGGL(bf_tile_kernel, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), tile_lds, st,
+                           p);
+        le = hipGetLastError();
     }
-    const int wpb = std::max(1, std::min(4, (int)(64 * 1024 / ((size_t)sort_n * 8))));
-    hipLaunchKernelGGL(bf_rerank_kernel, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb),
-                       (size_t)sort_n * 8 * wpb, st, base, queries, nq, d, cand, ncand, k, sort_n, out_ids, out_dist);
-    hipError_t e = hipGetLastError();
+    // stage 2 reads the candidates stage 1 wrote: launched only after it
+    if (le == hipSuccess) {
+        const int wpb = std::max(1, std::min(4, (int)(64 * 1024 / ((size_t)sort_n * 8))));
+        hipLaunchKernelGGL(bf_rerank_kernel, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb),
+                           (size_t)sort_n * 8 * wpb, st, base, queries, nq, d, cand, ncand, k, sort_n, out_ids,
+                           out_dist);
+    }
+    hipError_t e = le != hipSuccess ? le : hipGetLastError();
     hipFreeAsync(acc, st);
     hipFreeAsync(mu, st);
     hipFreeAsync(xnorm, st);
