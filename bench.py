@@ -561,14 +561,15 @@ def finish(args, nsg, ls, torch, dev, w, X, Q, Qd, ix32, ix16, graph, nav, rep, 
     # ---------------- rooflines ----------------
     # algorithmic bytes per query: rows gathered (N_dist x row bytes), the
     # neighbour rows read (entries + 1 per expansion, 4 B each), the query and
-    # the output; the FP16 search also re-reads its final pool in FP32 for the
-    # re-rank (pool entries x d x 4)
+    # the output; the FP16 search also reads FP32 rows for the re-rank,
+    # credited as the k rows any re-rank must read (the kernel reads the
+    # prefix of its pool that can hold the FP32 top k, at least k rows)
     def alg_bytes(c, row_bytes, rerank_rows):
         return (c["ndist"] * row_bytes + (c["nedges"] + c["hops"]) * 4 + nq * (d * 4 + k * 8)
                 + rerank_rows * d * 4)
 
     rb16 = -(-d // 8) * 16
-    b16 = alg_bytes(counts["f16_learned"], rb16, counts["f16_learned"]["pool"])
+    b16 = alg_bytes(counts["f16_learned"], rb16, nq * k)
     b32 = alg_bytes(counts["f32"], -(-d // 4) * 16, 0)
     ach16 = b16 / (ms16 / 1e3) / 1e9
     ach32 = b32 / (ms32 / 1e3) / 1e9

@@ -70,7 +70,9 @@ const char *nsg_last_error(void);
  *            1 for BF16 / FP16; s_j = 1 for an all-zero column) unless
  *            `scales` (device, [d]) is given; codes are round-to-nearest-even
  *            of base/s_j with saturation.  The FP32 rows are kept as well: they
- *            re-rank the final pool exactly.
+ *            re-rank the final pool exactly (only the prefix of the pool that
+ *            can hold the FP32 top k, by a bound on the stored format's error
+ *            computed here: the same result as re-ranking the whole pool).
  * The library copies base and graph into its own padded layout; the caller
  * may free its buffers after synchronising `stream`.  Graph entries must be
  * < n or the sentinel, nav < n (checked on the device; a violation returns
@@ -267,7 +269,8 @@ int nsg_autotune(const nsg_index *idx, const float *queries, int64_t nq, int32_t
 /*
  * Exact k nearest base rows of every query by squared l2 distance, ordered by
  * (distance, id).  Candidates come from FP32 matrix-core tiles
- * (|q|^2 + |x|^2 - 2 q.x), over-fetched, then re-ranked with exact FP32
+ * (|x - mu|^2 - 2 (q - mu).(x - mu) with mu the base mean: the squared
+ * distance minus a per-query constant), over-fetched, then re-ranked with exact FP32
  * differences (sum of (q_j - x_j)^2).  exclude_self != 0: queries are the base
  * rows themselves and query i never returns row i (kNN graph).  base[n][d],
  * queries[nq][d] FP32; out_ids / out_dist [nq][k].  1 <= k <= 160.  Scratch

@@ -117,6 +117,50 @@ __global__ void encode_kernel(const float *x, int64_t n, int d, int ld, const fl
     }
 }
 
+// Bound E of the index for the prefix re-rank: the maximum over rows of
+// ||xhat - x|| + 2^-22 ||xhat||, where xhat is the stored row as the search
+// decodes it (code times scale; the FP32 row itself for FP32 storage).  The
+// first term bounds | ||q - x|| - ||q - xhat|| | (triangle inequality); the
+// second covers a decode whose product s * c is rounded before the
+// difference.  Each row sum is scaled by 1 + 2^-12 for its own rounding
+// (d <= 1024 additions, one rounding per difference and per sqrt).  One
+// wave per row; the result is the float bit pattern in *out (atomic max:
+// non-negative floats order like their bits).
+__global__ void rr_eta_kernel(const float *x, int64_t n, int d, int ld, const float *s, int storage,
+                              const void *codes, int row_elems, unsigned int *out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); r < n; r += waves) {
+        float S = 0.0f, N = 0.0f;
+        for (int j = lane; j < d; j += 64) {
+            const float xv = x[r * ld + j];
+            float c = xv, sj = 1.0f;
+            if (storage != NSG_F32) {
+                const int64_t e = r * row_elems + j;
+                if (storage == NSG_F16)
+                    c = (float)__builtin_bit_cast(_Float16, reinterpret_cast<const uint16_t *>(codes)[e]);
+                else if (storage == NSG_BF16)
+                    c = __uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(codes)[e] << 16);
+                else
+                    c = __builtin_amdgcn_cvt_pk_f32_fp8((int)reinterpret_cast<const uint8_t *>(codes)[e], false)[0];
+                sj = s[j];
+            }
+            const float t = fmaf(sj, c, -xv);
+            const float h = sj * c;
+            S = fmaf(t, t, S);
+            N = fmaf(h, h, N);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            S += __shfl_xor(S, o);
+            N += __shfl_xor(N, o);
+        }
+        if (lane == 0) {
+            const float eta = (sqrtf(S) + 0x1p-22f * sqrtf(N)) * (1.0f + 0x1p-12f);
+            atomicMax(out, __float_as_uint(eta));
+        }
+    }
+}
+
 static int grid_for(int64_t cnt) {
     int64_t b = (cnt + 255) / 256;
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65536);
@@ -248,6 +292,23 @@ extern "C" int nsg_load_index(const float *base, int64_t n, int32_t d, const uin
     }
     e = hipGetLastError();
     if (e != hipSuccess) return cleanup(fail(NSG_EDEVICE, "load kernels failed: %s", hipGetErrorString(e)));
+    {
+        unsigned int *dmax = nullptr, hmax = 0;
+        if (hipMalloc(&dmax, sizeof(*dmax)) != hipSuccess) return cleanup(fail(NSG_ENOMEM, "alloc failed"));
+        e = hipMemsetAsync(dmax, 0, sizeof(*dmax), st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(rr_eta_kernel, dim3((unsigned)std::min<int64_t>((n + 3) / 4, 8192)), dim3(256), 0, st,
+                               ix->base_f32, n, d, ld32, ix->scales, (int)storage, ix->base_lp,
+                               ix->row_chunks * epc, dmax);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&hmax, dmax, sizeof(hmax), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        hipFree(dmax);
+        if (e != hipSuccess) return cleanup(fail(NSG_EDEVICE, "re-rank bound failed: %s", hipGetErrorString(e)));
+        const float eta = __builtin_bit_cast(float, hmax);
+        ix->rr_eta = eta < INFINITY ? eta : -1.0f;   // NaN or inf rows: re-rank whole pools
+    }
     *out = ix;
     return NSG_OK;
 }

@@ -62,6 +62,11 @@ struct nsg_index {
     void *base_lp = nullptr;     // [n][row_chunks * 16 bytes] for reduced formats
     float *scales = nullptr;     // [row_chunks_f32 * 4]
     uint32_t *graph = nullptr;   // [n][R_pad]
+    // bound E on | ||q - x_i|| - (walk distance of row i)^(1/2) | from the
+    // stored format (max_i ||xhat_i - x_i|| plus an absolute term for the
+    // decode's rounding), used to re-rank only the prefix of the pool that can
+    // hold the FP32 top k; < 0: unknown (the whole pool is re-ranked)
+    float rr_eta = -1.0f;
     int device = 0;
     nsg::StopModel stop;
     // live search graphs captured with the early stop (they hold the model's

@@ -93,6 +93,8 @@ int launch_search(const SearchArgs &a) {
     p.L_cap = a.L_cap;
     p.hash_bits = a.hash_bits;
     p.rerank = a.rerank;
+    p.rr_eta = ix->rr_eta;
+    p.rr_rho = (float)(ix->d + 4) * 0x1p-24f;
     p.hops = a.hops;
     p.ndist = a.ndist;
     p.nedges = a.nedges;

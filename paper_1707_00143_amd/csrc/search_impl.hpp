@@ -22,6 +22,8 @@ struct KParams {
     float *out_dist;
     int L_cap, L_alloc, hash_bits, lds_per_wave;
     int rerank;
+    float rr_eta;                // the index's bound E (< 0: re-rank the whole pool)
+    float rr_rho;                // relative rounding bound of a computed squared distance, (d + 4) 2^-24
     unsigned int *counter;
     int32_t *clamped;            // queries whose k / L were clamped into range, or NULL
     int64_t *hops, *ndist, *nedges;
@@ -103,6 +105,34 @@ __device__ inline void rerank_dist(const KParams &p, const float *q, uint64_t *p
             if (li == 0 && ok[u]) pool[r0 + 4 * u + g] = mk_key(acc[u], id[u]);
         wave_sync();
     }
+}
+
+// Entries of the walk-sorted pool that the FP32 re-rank has to see for its
+// top kq: the prefix with walk distance <= B.  With rho the relative bound of
+// a computed squared distance (walk and re-rank alike), E the index's bound on
+// | ||q - x|| - ||q - xhat|| | plus the decode's absolute rounding, and W the
+// kq-th walk distance: the first kq entries have exact distance at most
+// a = sqrt(W / (1 - rho)) + E, so re-rank distances at most
+// (1 + rho) a^2; an entry with walk distance above
+// B = (1 + rho) (sqrt((1 + rho) / (1 - rho)) a + E)^2 has exact distance
+// above sqrt(B / (1 + rho)) - E and a re-rank distance strictly above
+// (1 + rho) a^2, so it ranks after those kq entries whatever its id.  B gets
+// a relative slack of 2^-12 for its own rounding.  Returns size when the bound
+// is unknown or not finite.
+__device__ __attribute__((noinline)) int rerank_prefix(const KParams &p, const uint64_t *pool, int size, int kq, int lane) {
+    if (p.rr_eta < 0.0f || kq <= 0 || size <= kq) return kq <= 0 ? 0 : size;
+    const float rho = p.rr_rho;
+    const float W = key_dist(pool[kq - 1]);
+    const float a = sqrtf(W / (1.0f - rho)) + p.rr_eta;
+    const float t = sqrtf((1.0f + rho) / (1.0f - rho)) * a + p.rr_eta;
+    const float B = (1.0f + rho) * t * t * (1.0f + 0x1p-12f);
+    if (!(B < INFINITY)) return size;
+    int m = 0;
+    for (int j0 = 0; j0 < size; j0 += 64) {
+        const int j = j0 + lane;
+        m += __popcll(__ballot(j < size && key_dist(pool[j]) <= B));
+    }
+    return m > kq ? m : kq;
 }
 
 // ascending bitonic sort of pool[0..n) in LDS (n <= 1024), padding with KEY_NONE
@@ -505,8 +535,9 @@ search_kernel(KParams p) {
         }
         if (p.rerank) {
             wave_sync();
-            rerank_dist(p, q, pool, size, lane);
-            lds_sort(pool, size, p.L_alloc, lane);
+            const int m = rerank_prefix(p, pool, size, kq, lane);
+            rerank_dist(p, q, pool, m, lane);
+            lds_sort(pool, m, p.L_alloc, lane);
         }
         for (int j = lane; j < kq; j += 64) {
             bool ok = j < size;
