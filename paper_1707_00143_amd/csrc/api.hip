@@ -124,12 +124,15 @@ __global__ void encode_kernel(const float *x, int64_t n, int d, int ld, const fl
 // second covers a decode whose product s * c is rounded before the
 // difference.  Each row sum is scaled by 1 + 2^-12 for its own rounding
 // (d <= 1024 additions, one rounding per difference and per sqrt).  One
-// wave per row; the result is the float bit pattern in *out (atomic max:
-// non-negative floats order like their bits).
+// wave per row; the maximum is kept per wave, then per block (LDS), and one
+// atomic max per block leaves it as the float bit pattern in *out
+// (non-negative floats order like their bits).  Block size 256.
 __global__ void rr_eta_kernel(const float *x, int64_t n, int d, int ld, const float *s, int storage,
                               const void *codes, int row_elems, unsigned int *out) {
+    __shared__ unsigned int wmax[4];
     const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    unsigned int best = 0u;
     for (int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); r < n; r += waves) {
         float S = 0.0f, N = 0.0f;
         for (int j = lane; j < d; j += 64) {
@@ -154,10 +157,16 @@ __global__ void rr_eta_kernel(const float *x, int64_t n, int d, int ld, const fl
             S += __shfl_xor(S, o);
             N += __shfl_xor(N, o);
         }
-        if (lane == 0) {
-            const float eta = (sqrtf(S) + 0x1p-22f * sqrtf(N)) * (1.0f + 0x1p-12f);
-            atomicMax(out, __float_as_uint(eta));
-        }
+        const float eta = (sqrtf(S) + 0x1p-22f * sqrtf(N)) * (1.0f + 0x1p-12f);
+        const unsigned int b = __float_as_uint(eta);
+        best = b > best ? b : best;
+    }
+    if (lane == 0) wmax[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int m = wmax[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = wmax[w] > m ? wmax[w] : m;
+        atomicMax(out, m);
     }
 }
 
