@@ -6,10 +6,11 @@
 // v_mfma_f32_16x16x4f32, turned into rank values, and every value below the
 // query's current threshold is appended to that query's candidate buffer
 // (device memory: appends are rare once the threshold is tight).  A buffer
-// that could overflow on the next tile is sorted (in the wave's LDS scratch)
-// and cut back to its Kp best, which tightens the threshold (the buffer
-// holds Kp + 2 tiles, so sorts are rare once the threshold is tight).  Each
-// block writes Kp candidates per query for its split.
+// that could overflow on the next tile is cut back to its Kp best by a
+// radix select over the rank values (ballot counts, in registers), which
+// tightens the threshold (the buffer holds Kp + 2 tiles, so cuts are rare
+// once the threshold is tight).  Each block writes the ids of its Kp best per
+// query for its split.
 //  * d <= 128 (bf_wide_kernel): 4 waves x 32 queries per block; each wave
 //    keeps its centred queries as matrix-core operands in registers for the
 //    whole scan, owns all 64 rows of a tile and appends and compacts only its
@@ -131,6 +132,74 @@ __device__ inline void wave_sort_buf(uint64_t *buf, int cnt, int cap, int lane) 
         }
 }
 
+// Order-preserving map of a float to 32 bits (ascending keys = ascending
+// values, negative values included).
+__device__ inline uint32_t ord_bits(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float ord_float(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__device__ inline void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Keep the Kp entries of buf[0..c) with the smallest rank values (the high
+// words of the keys; ties at the cut taken in buffer order) in buf[0..Kp),
+// in no particular order, and return the Kp-th smallest high word.  c in
+// [Kp, 512].  One wave: the high word of the Kp-th smallest is found bit by
+// bit from the top (a radix select counting with ballots), then the kept
+// entries are written to the front.  Every load precedes every store (the
+// stores depend on ballots over all loaded keys).
+__device__ __attribute__((noinline)) uint32_t wave_keep_smallest(uint64_t *buf, int c, int Kp, int lane) {
+    constexpr int M = 8;
+    uint64_t key[M];
+    bool ok[M];
+#pragma unroll
+    for (int e = 0; e < M; ++e) {
+        const int j = e * 64 + lane;
+        ok[e] = j < c;
+        key[e] = ok[e] ? buf[j] : 0ull;
+    }
+    uint32_t prefix = 0u;
+    int need = Kp;   // rank of the target among the entries that match the prefix so far
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t above = b == 31 ? 0u : (0xFFFFFFFFu << (b + 1));
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < M; ++e) {
+            if (e * 64 >= c) break;
+            const uint32_t h = (uint32_t)(key[e] >> 32);
+            cnt += __popcll(__ballot(ok[e] && (h & above) == prefix && ((h >> b) & 1u) == 0u));
+        }
+        if (cnt < need) {
+            need -= cnt;
+            prefix |= 1u << b;
+        }
+    }
+    // entries below the prefix value go to [0, Kp - need), the first `need`
+    // equal to it to [Kp - need, Kp)
+    const uint64_t below = (1ull << lane) - 1ull;
+    int at_lt = 0, at_eq = Kp - need, eq_seen = 0;
+#pragma unroll
+    for (int e = 0; e < M; ++e) {
+        if (e * 64 >= c) break;
+        const uint32_t h = (uint32_t)(key[e] >> 32);
+        const bool lt = ok[e] && h < prefix, eq = ok[e] && h == prefix;
+        const uint64_t blt = __ballot(lt), beq = __ballot(eq);
+        const int rl = __popcll(blt & below), re = __popcll(beq & below);
+        if (lt) buf[at_lt + rl] = key[e];
+        if (eq && eq_seen + re < need) buf[at_eq + eq_seen + re] = key[e];
+        at_lt += __popcll(blt);
+        eq_seen += __popcll(beq);
+    }
+    return prefix;
+}
+
 // Stage 1 for d > 128: a block owns 64 queries (16 per wave), and each
 // 32-dim chunk of the queries and of a 64-row base tile is staged through LDS.
 __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
@@ -139,14 +208,12 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
     float *Qs = Xs + KB * KPAD;                                 // [KB][KPAD]
     float *thr = Qs + KB * KPAD;                                // [BQ]
     int *cnt = reinterpret_cast<int *>(thr + BQ);               // [BQ]
-    uint64_t *scratch = reinterpret_cast<uint64_t *>(cnt + BQ); // [4][cap]: one sort buffer per wave
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t q0 = (int64_t)blockIdx.x * BQ;
     const int split = blockIdx.y;
     const int64_t xb = (int64_t)split * p.split_len;
     const int64_t xe = std::min<int64_t>(p.n, xb + p.split_len);
     uint64_t *buf = p.cand_buf + ((int64_t)blockIdx.x * p.nsplit + split) * (int64_t)BQ * p.cap;
-    uint64_t *sw = scratch + (size_t)w * p.cap;
     if (tid < BQ) { thr[tid] = INFINITY; cnt[tid] = 0; }
     bsync();
     const int rq = lane & 15, kq = lane >> 4;   // MFMA operand row / k group of this lane
@@ -208,46 +275,32 @@ __global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
         for (int r = w; r < BQ; r += 4) {
             int c = cnt[r];
             if (c > p.cap - BX) {
-                uint64_t *br = buf + (size_t)r * p.cap;
-                for (int j = lane; j < c; j += 64) sw[j] = br[j];
-                wave_sort_buf(sw, c, p.cap, lane);
-                for (int j = lane; j < p.Kp; j += 64) br[j] = sw[j];
+                // keys carry non-negative distances: their high words order like the values
+                const uint32_t t = wave_keep_smallest(buf + (size_t)r * p.cap, c, p.Kp, lane);
                 if (lane == 0) {
                     cnt[r] = p.Kp;
-                    thr[r] = __uint_as_float((uint32_t)(sw[p.Kp - 1] >> 32));
+                    thr[r] = __uint_as_float(t);
                 }
             }
         }
         bsync();
     }
-    // final: sort each buffer, write Kp candidates (sentinel padded)
+    // final: cut each buffer to its Kp smallest, write their ids (order free:
+    // stage 2 sorts; sentinel padded)
     for (int r = w; r < BQ; r += 4) {
         int64_t qi = q0 + r;
         if (qi >= p.nq) continue;
         int c = cnt[r];
-        const uint64_t *br = buf + (size_t)r * p.cap;
-        for (int j = lane; j < c; j += 64) sw[j] = br[j];
-        wave_sort_buf(sw, c, p.cap, lane);
+        uint64_t *br = buf + (size_t)r * p.cap;
+        if (c > p.Kp) {
+            wave_keep_smallest(br, c, p.Kp, lane);
+            wave_fence();
+        }
         uint32_t *dst = p.cand_ids + (qi * p.nsplit + split) * (int64_t)p.Kp;
         for (int j = lane; j < p.Kp; j += 64)
-            dst[j] = j < c ? (uint32_t)(sw[j] & 0xFFFFFFFFu) : NSG_SENT;
+            dst[j] = j < c ? (uint32_t)(br[j] & 0xFFFFFFFFu) : NSG_SENT;
+        wave_fence();
     }
-}
-
-// Order-preserving map of a float to 32 bits (ascending keys = ascending
-// values, negative values included).
-__device__ inline uint32_t ord_bits(float v) {
-    const uint32_t u = __float_as_uint(v);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ inline float ord_float(uint32_t k) {
-    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
-}
-
-__device__ inline void wave_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // Stage 1 for d <= 128 with wide query tiles.  Every wave owns QW queries
@@ -278,7 +331,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
     float *mus = Xs + 2 * BX * LD;                                        // [DP] centre, 0 past d
     float *thr_s = mus + DP;                                              // [4][QW]
     int *cnt_s = reinterpret_cast<int *>(thr_s + 4 * QW);                 // [4][QW]
-    uint64_t *scratch = reinterpret_cast<uint64_t *>(cnt_s + 4 * QW);     // [4][cap]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int rq = lane & 15, kq = lane >> 4;
     const int64_t qb = (int64_t)blockIdx.x * 4 * QW;   // first query of the block
@@ -290,7 +342,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
                     (int64_t)w * QW * p.cap;
     float *thr_w = thr_s + w * QW;
     int *cnt_w = cnt_s + w * QW;
-    uint64_t *sw = scratch + (size_t)w * p.cap;
     for (int j = tid; j < DP; j += 256) mus[j] = j < p.d ? p.mu[j] : 0.0f;
     if (lane < QW) {
         thr_w[lane] = qw0 + lane < p.nq ? INFINITY : -INFINITY;
@@ -451,11 +502,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
                 const int r = __builtin_ctzll(full);
                 full &= full - 1;
                 const int c = cnt_w[r];
-                uint64_t *br = buf + (size_t)r * p.cap;
-                for (int j = lane; j < c; j += 64) sw[j] = br[j];
-                wave_sort_buf(sw, c, p.cap, lane);
-                for (int j = lane; j < p.Kp; j += 64) br[j] = sw[j];
-                const float tnew = ord_float((uint32_t)(sw[p.Kp - 1] >> 32));
+                const float tnew = ord_float(wave_keep_smallest(buf + (size_t)r * p.cap, c, p.Kp, lane));
                 wave_fence();
                 if (lane == 0) {
                     cnt_w[r] = p.Kp;
@@ -469,16 +516,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
         cur ^= 1;
         bsync();
     }
-    // final: sort each buffer of the wave, write Kp candidates (sentinel padded)
+    // final: cut each buffer of the wave to its Kp smallest, write their ids
+    // (order free: stage 2 sorts; sentinel padded)
     for (int r = 0; r < QW; ++r) {
         const int64_t qi = qw0 + r;
         if (qi >= p.nq) break;
         const int c = cnt_w[r];
-        const uint64_t *br = buf + (size_t)r * p.cap;
-        for (int j = lane; j < c; j += 64) sw[j] = br[j];
-        wave_sort_buf(sw, c, p.cap, lane);
+        uint64_t *br = buf + (size_t)r * p.cap;
+        if (c > p.Kp) {
+            wave_keep_smallest(br, c, p.Kp, lane);
+            wave_fence();
+        }
         uint32_t *dst = p.cand_ids + (qi * p.nsplit + split) * (int64_t)p.Kp;
-        for (int j = lane; j < p.Kp; j += 64) dst[j] = j < c ? (uint32_t)(sw[j] & 0xFFFFFFFFu) : NSG_SENT;
+        for (int j = lane; j < p.Kp; j += 64) dst[j] = j < c ? (uint32_t)(br[j] & 0xFFFFFFFFu) : NSG_SENT;
         wave_fence();
     }
 }
@@ -539,18 +589,18 @@ struct WideKernel {
 };
 
 template <int DP, bool VEC>
-WideKernel wide_kernel_t(int cap) {
+WideKernel wide_kernel_t() {
     return {(const void *)bf_wide_kernel<DP, kWideQW, VEC>,
-            (size_t)2 * BX * (DP + 4) * 4 + (size_t)DP * 4 + (size_t)4 * kWideQW * 8 + (size_t)4 * cap * 8};
+            (size_t)2 * BX * (DP + 4) * 4 + (size_t)DP * 4 + (size_t)4 * kWideQW * 8};
 }
 
 template <bool VEC>
-WideKernel wide_kernel_v(int d, int cap) {
+WideKernel wide_kernel_v(int d) {
     const int DP = (d + 31) / 32 * 32;
-    return DP == 32 ? wide_kernel_t<32, VEC>(cap)
-           : DP == 64 ? wide_kernel_t<64, VEC>(cap)
-           : DP == 96 ? wide_kernel_t<96, VEC>(cap)
-                      : wide_kernel_t<128, VEC>(cap);
+    return DP == 32 ? wide_kernel_t<32, VEC>()
+           : DP == 64 ? wide_kernel_t<64, VEC>()
+           : DP == 96 ? wide_kernel_t<96, VEC>()
+                      : wide_kernel_t<128, VEC>();
 }
 
 }  // namespace nsg
@@ -584,9 +634,9 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     // short); at least a few tiles per split
     int64_t want;
     WideKernel wk{};
-    const size_t tile_lds = (size_t)2 * KB * KPAD * 4 + BQ * 8 + (size_t)4 * cap * 8;
+    const size_t tile_lds = (size_t)2 * KB * KPAD * 4 + BQ * 8;
     if (wide) {
-        wk = vec4 ? wide_kernel_v<true>(d, cap) : wide_kernel_v<false>(d, cap);
+        wk = vec4 ? wide_kernel_v<true>(d) : wide_kernel_v<false>(d);
         NSG_HIP(hipFuncSetAttribute(wk.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wk.lds));
         int dev = 0, cus = 0, per_cu = 0;
         NSG_HIP(hipGetDevice(&dev));
