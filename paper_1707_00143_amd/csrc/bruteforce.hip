@@ -15,8 +15,9 @@
 //    keeps its centred queries as matrix-core operands in registers for the
 //    whole scan, owns all 64 rows of a tile and appends and compacts only its
 //    own queries; the base tile is staged once per block, double buffered.
-//  * d > 128 (bf_tile_kernel): 4 waves x 16 queries per block; 32-dim chunks
-//    of queries and base rows are staged through LDS.
+//  * d > 128 (bf_chunked_kernel): 4 waves x 32 queries per block and
+//    128-row tiles; 32-dim chunks of the queries and of the tile are staged
+//    once per block, double buffered.
 // Stage 2: per query (one wave), exact FP32 squared distances sum (q_j-x_j)^2
 // of all candidates of all splits, bitonic sort by (distance, id), first k.
 // Centring keeps the cancellation error of the inner-product form small;
@@ -29,21 +30,19 @@ namespace nsg {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BQ = 64, BX = 64, KB = 32, KPAD = 68;
+constexpr int BX = 64;   // rows per base tile of the wide kernel
 
 struct BFParams {
     const float *base, *queries;
     const float *mu;       // [d] base mean
     const float *xnorm;    // [n] |x - mu|^2
-    const float *qnorm;    // [nq] |q - mu|^2
     int64_t n, nq;
     int d, Kp, cap;
     int64_t split_len;
     int nsplit;
     int exclude_self;
-    int vec4;              // rows 16-byte aligned (d % 4 == 0, aligned base): vector loads
     uint32_t *cand_ids;    // [nq][nsplit][Kp]
-    uint64_t *cand_buf;    // [qtiles][nsplit][BQ][cap] candidate buffers
+    uint64_t *cand_buf;    // [qtiles][nsplit][128 queries][cap] candidate buffers
 };
 
 __device__ inline void bsync() { __syncthreads(); }
@@ -198,109 +197,6 @@ __device__ __attribute__((noinline)) uint32_t wave_keep_smallest(uint64_t *buf, 
         eq_seen += __popcll(beq);
     }
     return prefix;
-}
-
-// Stage 1 for d > 128: a block owns 64 queries (16 per wave), and each
-// 32-dim chunk of the queries and of a 64-row base tile is staged through LDS.
-__global__ void __launch_bounds__(256) bf_tile_kernel(BFParams p) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    float *Xs = reinterpret_cast<float *>(smem);               // [KB][KPAD]
-    float *Qs = Xs + KB * KPAD;                                 // [KB][KPAD]
-    float *thr = Qs + KB * KPAD;                                // [BQ]
-    int *cnt = reinterpret_cast<int *>(thr + BQ);               // [BQ]
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t q0 = (int64_t)blockIdx.x * BQ;
-    const int split = blockIdx.y;
-    const int64_t xb = (int64_t)split * p.split_len;
-    const int64_t xe = std::min<int64_t>(p.n, xb + p.split_len);
-    uint64_t *buf = p.cand_buf + ((int64_t)blockIdx.x * p.nsplit + split) * (int64_t)BQ * p.cap;
-    if (tid < BQ) { thr[tid] = INFINITY; cnt[tid] = 0; }
-    bsync();
-    const int rq = lane & 15, kq = lane >> 4;   // MFMA operand row / k group of this lane
-    // |q - mu|^2 of the 4 query rows this lane's accumulators hold
-    float qn[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t qi = q0 + 16 * w + 4 * kq + i;
-        qn[i] = qi < p.nq ? p.qnorm[qi] : 0.0f;
-    }
-    for (int64_t x0 = xb; x0 < xe; x0 += BX) {
-        f32x4 acc[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k0 = 0; k0 < p.d; k0 += KB) {
-            // stage centred Q and X chunks, k-major: 64 rows x 32 dims each
-#pragma unroll
-            for (int it = 0; it < (BQ * KB) / 256; ++it) {
-                int e = tid + it * 256;
-                int r = e / KB, kk = e % KB;
-                int j = k0 + kk;
-                int64_t qi = q0 + r, xi = x0 + r;
-                float mj = j < p.d ? p.mu[j] : 0.0f;
-                Qs[kk * KPAD + r] = (qi < p.nq && j < p.d) ? p.queries[qi * p.d + j] - mj : 0.0f;
-                Xs[kk * KPAD + r] = (xi < xe && j < p.d) ? p.base[xi * p.d + j] - mj : 0.0f;
-            }
-            bsync();
-#pragma unroll
-            for (int kk = 0; kk < KB; kk += 4) {
-                float a = Qs[(kk + kq) * KPAD + 16 * w + rq];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    float b = Xs[(kk + kq) * KPAD + 16 * t + rq];
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
-                }
-            }
-            bsync();
-        }
-        // epilogue: lane holds rows 4*kq + i of this wave's 16 queries, column rq of tile t
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            int64_t xi = x0 + 16 * t + rq;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int r = 16 * w + 4 * kq + i;
-                int64_t qi = q0 + r;
-                if (xi < xe && qi < p.nq && !(p.exclude_self && xi == qi)) {
-                    float dd = qn[i] + p.xnorm[xi] - 2.0f * acc[t][i];
-                    dd = fmaxf(dd, 0.0f);
-                    if (dd < thr[r]) {
-                        int s = atomicAdd(&cnt[r], 1);
-                        buf[(size_t)r * p.cap + s] = bkey(dd, (uint32_t)xi);
-                    }
-                }
-            }
-        }
-        bsync();
-        // compaction when the next tile could overflow: wave w handles queries w, w+4, ...
-        for (int r = w; r < BQ; r += 4) {
-            int c = cnt[r];
-            if (c > p.cap - BX) {
-                // keys carry non-negative distances: their high words order like the values
-                const uint32_t t = wave_keep_smallest(buf + (size_t)r * p.cap, c, p.Kp, lane);
-                if (lane == 0) {
-                    cnt[r] = p.Kp;
-                    thr[r] = __uint_as_float(t);
-                }
-            }
-        }
-        bsync();
-    }
-    // final: cut each buffer to its Kp smallest, write their ids (order free:
-    // stage 2 sorts; sentinel padded)
-    for (int r = w; r < BQ; r += 4) {
-        int64_t qi = q0 + r;
-        if (qi >= p.nq) continue;
-        int c = cnt[r];
-        uint64_t *br = buf + (size_t)r * p.cap;
-        if (c > p.Kp) {
-            wave_keep_smallest(br, c, p.Kp, lane);
-            wave_fence();
-        }
-        uint32_t *dst = p.cand_ids + (qi * p.nsplit + split) * (int64_t)p.Kp;
-        for (int j = lane; j < p.Kp; j += 64)
-            dst[j] = j < c ? (uint32_t)(br[j] & 0xFFFFFFFFu) : NSG_SENT;
-        wave_fence();
-    }
 }
 
 // Stage 1 for d <= 128 with wide query tiles.  Every wave owns QW queries
@@ -533,6 +429,233 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
     }
 }
 
+// Stage 1 for d > 128 (bf_chunked_kernel): 4 waves x 32 queries per block and
+// 128-row base tiles; each wave owns all 128 rows of a tile for its queries
+// (2 row groups x 8 column groups of accumulators).  The dimensions stream
+// in chunks of 32: the block stages each chunk of its 128 centred queries
+// and of the tile's 128 centred rows in LDS (double buffered, one barrier per
+// chunk; the next chunk is loaded into registers in two halves while the
+// current one is multiplied).  The query chunks are read again for every
+// tile (from L2 or the last-level cache); a 128 x 128 output tile keeps that
+// traffic at 64 flops per byte.  Operand reads are 16 bytes wide through the
+// same permutation of the dimensions as the wide kernel (lane group kq takes
+// dims [8 kq, 8 kq + 8) of each chunk).  Rank values, appends, cuts and the
+// final write are those of the wide kernel.
+constexpr int CQ = 128, CX = 128, KC = 32, CLD = KC + 4;
+
+template <bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) bf_chunked_kernel(BFParams p) {
+    constexpr int QW = 32, G = 2, T = 8, F4 = KC / 4;   // queries per wave, row / column groups, pieces per row
+    static_assert(256 % F4 == 0 && (CQ * F4) % 256 == 0 && CQ == CX, "staging shape");
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *As = reinterpret_cast<float *>(smem);                       // [2][CQ][CLD]
+    float *Bs = As + 2 * CQ * CLD;                                     // [2][CX][CLD]
+    float *thr_s = Bs + 2 * CX * CLD;                                  // [4][QW]
+    int *cnt_s = reinterpret_cast<int *>(thr_s + 4 * QW);              // [4][QW]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int rq = lane & 15, kq = lane >> 4;
+    const int64_t qb = (int64_t)blockIdx.x * CQ;
+    const int64_t qw0 = qb + (int64_t)w * QW;
+    const int split = blockIdx.y;
+    const int64_t xb = (int64_t)split * p.split_len;
+    const int64_t xe = std::min<int64_t>(p.n, xb + p.split_len);
+    uint64_t *buf = p.cand_buf + ((int64_t)blockIdx.x * p.nsplit + split) * (int64_t)CQ * p.cap +
+                    (int64_t)w * QW * p.cap;
+    float *thr_w = thr_s + w * QW;
+    int *cnt_w = cnt_s + w * QW;
+    const int nchunk = (p.d + KC - 1) / KC;
+    if (lane < QW) {
+        thr_w[lane] = qw0 + lane < p.nq ? INFINITY : -INFINITY;
+        cnt_w[lane] = 0;
+    }
+    const int qrows = (int)std::min<int64_t>(CQ, p.nq - qb);   // >= 1
+    // one operand's chunk: 128 rows x 32 dims = 1024 pieces of 16 bytes, 4 per
+    // thread; piece f = tid + 256 u is row f / 8, dims k0 + 4 (f % 8) .. + 3.
+    // Clamped in-range addresses and a select: rows past the end and dims past
+    // d give 0.
+    float4 xr[4];
+    float mv[4];   // the centre at this thread's 4 dims of the chunk (see store_op)
+    auto load_op = [&](const float *rows, int nrows, int k0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = k0 + 4 * (tid % F4) + e;
+            const float m = p.mu[std::min(j, p.d - 1)];
+            mv[e] = j < p.d ? m : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int f = tid + 256 * u;
+            const int r = f / F4, j = k0 + 4 * (f % F4);
+            const int rr = std::min(r, nrows - 1);
+            if (VEC) {
+                const float4 v = *reinterpret_cast<const float4 *>(rows + (int64_t)rr * p.d + std::min(j, p.d - 4));
+                xr[u] = r < nrows && j < p.d ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            } else {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float x = rows[(int64_t)rr * p.d + std::min(j + e, p.d - 1)];
+                    v[e] = r < nrows && j + e < p.d ? x : 0.0f;
+                }
+                xr[u] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+    };
+    // centred into LDS; a thread's pieces all sit at dims k0 + c .. + 3 with
+    // c = 4 (tid % 8), so load_op reads those 4 values of the centre once,
+    // with the operand (0 past d)
+    auto store_op = [&](float *dst) {
+        const int c = 4 * (tid % F4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = (tid + 256 * u) / F4;
+            float4 v = xr[u];
+            v.x -= mv[0]; v.y -= mv[1]; v.z -= mv[2]; v.w -= mv[3];
+            *reinterpret_cast<float4 *>(dst + r * CLD + c) = v;
+        }
+    };
+    const float *qrow0 = p.queries + qb * p.d;
+    auto tile_rows = [&](int64_t x0) { return (int)std::min<int64_t>(CX, xe - x0); };
+    bsync();   // counters visible
+    float thr[G][4];
+    auto load_thr = [&]() {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) thr[g][i] = thr_w[16 * g + 4 * kq + i];
+    };
+    load_thr();
+    if (xb < xe) {
+        load_op(qrow0, qrows, 0);
+        store_op(As);
+        load_op(p.base + xb * p.d, tile_rows(xb), 0);
+        store_op(Bs);
+    }
+    bsync();
+    int cur = 0;
+    for (int64_t x0 = xb; x0 < xe; x0 += CX) {
+        float xn[T];
+        {
+            const int rows = tile_rows(x0);
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const int r = 16 * t + rq;
+                const float u = p.xnorm[x0 + std::min(r, rows - 1)];
+                xn[t] = r < rows ? u : INFINITY;
+            }
+        }
+        f32x4 acc[G][T];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[g][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int ch = 0; ch < nchunk; ++ch) {
+            // the chunk staged next: the following chunk of this tile, else
+            // the first chunk of the next tile
+            const bool more = ch + 1 < nchunk || x0 + CX < xe;
+            const int64_t nx0 = ch + 1 < nchunk ? x0 : x0 + CX;
+            const int nk0 = ch + 1 < nchunk ? (ch + 1) * KC : 0;
+            const float *Ac = As + cur * CQ * CLD, *Bc = Bs + cur * CX * CLD;
+            float *An = As + (cur ^ 1) * CQ * CLD, *Bn = Bs + (cur ^ 1) * CX * CLD;
+            if (more) load_op(qrow0, qrows, nk0);
+#pragma unroll
+            for (int s4 = 0; s4 < KC / 4; s4 += 4) {
+                if (s4 == 4 && more) {
+                    store_op(An);
+                    load_op(p.base + nx0 * p.d, tile_rows(nx0), nk0);
+                }
+                float4 a4[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    a4[g] = *reinterpret_cast<const float4 *>(Ac + (QW * w + 16 * g + rq) * CLD + 8 * kq + s4);
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const float4 b4 = *reinterpret_cast<const float4 *>(Bc + (16 * t + rq) * CLD + 8 * kq + s4);
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[g].x, b4.x, acc[g][t], 0, 0, 0);
+                        acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[g].y, b4.y, acc[g][t], 0, 0, 0);
+                        acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[g].z, b4.z, acc[g][t], 0, 0, 0);
+                        acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[g].w, b4.w, acc[g][t], 0, 0, 0);
+                    }
+                }
+            }
+            if (more) store_op(Bn);
+            cur ^= 1;
+            bsync();
+        }
+        // epilogue: lane holds queries 16 g + 4 kq + i of the wave, row 16 t + rq
+        // of the tile; rank values in place, a query's own row made +inf
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[g][t][i] = fmaf(-2.0f, acc[g][t][i], xn[t]);
+        if (p.exclude_self && x0 < qw0 + QW && qw0 < x0 + CX) {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (x0 + 16 * t + rq == qw0 + 16 * g + 4 * kq + i) acc[g][t][i] = INFINITY;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float m = acc[g][0][i];
+#pragma unroll
+                for (int t = 1; t < T; ++t) m = fminf(m, acc[g][t][i]);
+                if (m < thr[g][i]) {
+                    const int r = 16 * g + 4 * kq + i;
+#pragma unroll
+                    for (int t = 0; t < T; ++t) {
+                        const float v = acc[g][t][i];
+                        if (v < thr[g][i]) {
+                            const int slot = atomicAdd(&cnt_w[r], 1);
+                            buf[(size_t)r * p.cap + slot] =
+                                ((uint64_t)ord_bits(v) << 32) | (uint32_t)(x0 + 16 * t + rq);
+                        }
+                    }
+                }
+            }
+        wave_fence();
+        // cut this wave's buffers that could overflow on the next tile
+        uint64_t full = __builtin_amdgcn_ballot_w64(lane < QW && cnt_w[lane < QW ? lane : 0] > p.cap - CX);
+        if (full) {
+            while (full) {
+                const int r = __builtin_ctzll(full);
+                full &= full - 1;
+                const int c = cnt_w[r];
+                const float tnew = ord_float(wave_keep_smallest(buf + (size_t)r * p.cap, c, p.Kp, lane));
+                wave_fence();
+                if (lane == 0) {
+                    cnt_w[r] = p.Kp;
+                    thr_w[r] = tnew;
+                }
+                wave_fence();
+            }
+            load_thr();
+        }
+    }
+    // final: cut each buffer of the wave to its Kp smallest, write their ids
+    for (int r = 0; r < QW; ++r) {
+        const int64_t qi = qw0 + r;
+        if (qi >= p.nq) break;
+        const int c = cnt_w[r];
+        uint64_t *br = buf + (size_t)r * p.cap;
+        if (c > p.Kp) {
+            wave_keep_smallest(br, c, p.Kp, lane);
+            wave_fence();
+        }
+        uint32_t *dst = p.cand_ids + (qi * p.nsplit + split) * (int64_t)p.Kp;
+        for (int j = lane; j < p.Kp; j += 64) dst[j] = j < c ? (uint32_t)(br[j] & 0xFFFFFFFFu) : NSG_SENT;
+        wave_fence();
+    }
+}
+
 // one wave per query: exact distances of all candidates, sort, first k
 __global__ void __launch_bounds__(256) bf_rerank_kernel(const float *base, const float *queries, int64_t nq,
                                                         int d, const uint32_t *cand, int ncand, int k,
@@ -622,33 +745,33 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     // over-fetch margin 24 for the inner-product form's rounding; buffer of
     // Kp + two tiles (next power of two)
     const int Kp = (k + 24 + 31) / 32 * 32;
-    int cap = 1;
-    while (cap < Kp + 2 * BX) cap <<= 1;
-    // d <= 128: wide query tiles (4 waves x kWideQW queries per block)
+    // d <= 128: wide query tiles (4 waves x kWideQW queries, 64-row tiles);
+    // d > 128: chunked dimensions (4 waves x 32 queries, 128-row tiles)
     const bool wide = d <= 128;
-    const bool vec4 = d % 4 == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0;
-    const int bq = wide ? 4 * kWideQW : BQ;
+    const int tile = wide ? BX : CX;
+    int cap = 1;
+    while (cap < Kp + 2 * tile) cap <<= 1;
+    const bool vec4 = d % 4 == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(queries) & 15) == 0;
+    const int bq = wide ? 4 * kWideQW : CQ;
     const int64_t qtiles = (nq + bq - 1) / bq;
     // splits of the base: with fewer query tiles than resident blocks, enough
     // splits for one full round of blocks (fewer splits keep the exact pass
     // short); at least a few tiles per split
-    int64_t want;
     WideKernel wk{};
-    const size_t tile_lds = (size_t)2 * KB * KPAD * 4 + BQ * 8;
     if (wide) {
         wk = vec4 ? wide_kernel_v<true>(d) : wide_kernel_v<false>(d);
-        NSG_HIP(hipFuncSetAttribute(wk.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wk.lds));
-        int dev = 0, cus = 0, per_cu = 0;
-        NSG_HIP(hipGetDevice(&dev));
-        NSG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        NSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wk.fn, 256, wk.lds));
-        const int64_t slots = std::max<int64_t>(1, (int64_t)cus * per_cu);
-        want = std::max<int64_t>(1, slots / qtiles);
     } else {
-        NSG_HIP(hipFuncSetAttribute((const void *)bf_tile_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)tile_lds));
-        want = std::max<int64_t>(1, 2048 / qtiles);
+        const size_t lds = (size_t)4 * CQ * CLD * 4 + (size_t)8 * 32 * 4;
+        wk = {vec4 ? (const void *)bf_chunked_kernel<true> : (const void *)bf_chunked_kernel<false>, lds};
     }
+    NSG_HIP(hipFuncSetAttribute(wk.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wk.lds));
+    int dev = 0, cus = 0, per_cu = 0;
+    NSG_HIP(hipGetDevice(&dev));
+    NSG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    NSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wk.fn, 256, wk.lds));
+    const int64_t slots = std::max<int64_t>(1, (int64_t)cus * per_cu);
+    const int64_t want = std::max<int64_t>(1, slots / qtiles);
     int64_t max_split = std::max<int64_t>(1, n / (BX * 8));
     int nsplit = (int)std::min<int64_t>(std::min<int64_t>(want, max_split), std::max(1, 4096 / Kp));
     int64_t split_len = (n + nsplit - 1) / nsplit;
@@ -658,26 +781,22 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     int sort_n = 1;
     while (sort_n < ncand) sort_n <<= 1;
     if (sort_n * 8 > 64 * 1024) return fail(NSG_EUNSUPPORTED, "too many candidates per query (%d)", ncand);
-    float *mu = nullptr, *xnorm = nullptr, *qnorm = nullptr;
+    float *mu = nullptr, *xnorm = nullptr;
     float2 *acc = nullptr;
     uint32_t *cand = nullptr;
     uint64_t *cbuf = nullptr;
     NSG_HIP(hipMallocAsync((void **)&acc, sizeof(float2) * d * mean_blocks(n), st));
     NSG_HIP(hipMallocAsync((void **)&mu, sizeof(float) * d, st));
     NSG_HIP(hipMallocAsync((void **)&xnorm, sizeof(float) * n, st));
-    NSG_HIP(hipMallocAsync((void **)&qnorm, sizeof(float) * nq, st));
     NSG_HIP(hipMallocAsync((void **)&cand, sizeof(uint32_t) * nq * ncand, st));
     NSG_HIP(hipMallocAsync((void **)&cbuf, sizeof(uint64_t) * qtiles * nsplit * bq * cap, st));
     if (int rc = launch_mean(base, n, d, mu, acc, st)) return rc;
     hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, d, mu, xnorm);
-    if (!wide)   // the wide kernel ranks by |x - mu|^2 - 2 (q - mu).(x - mu): no query norms
-        hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, queries, nq, d, mu, qnorm);
     BFParams p{};
     p.base = base;
     p.queries = queries;
     p.mu = mu;
     p.xnorm = xnorm;
-    p.qnorm = qnorm;
     p.n = n;
     p.nq = nq;
     p.d = d;
@@ -688,16 +807,8 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     p.exclude_self = exclude_self ? 1 : 0;
     p.cand_ids = cand;
     p.cand_buf = cbuf;
-    p.vec4 = vec4 ? 1 : 0;
-    hipError_t le;
-    if (wide) {
-        void *args[] = {&p};
-        le = hipLaunchKernel(wk.fn, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), args, wk.lds, st);
-    } else {
-        hipLaunchKernelGGL(bf_tile_kernel, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), tile_lds, st,
-                           p);
-        le = hipGetLastError();
-    }
+    void *args[] = {&p};
+    const hipError_t le = hipLaunchKernel(wk.fn, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), args, wk.lds, st);
     // stage 2 reads the candidates stage 1 wrote: launched only after it
     if (le == hipSuccess) {
         const int wpb = std::max(1, std::min(4, (int)(64 * 1024 / ((size_t)sort_n * 8))));
@@ -709,7 +820,6 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     hipFreeAsync(acc, st);
     hipFreeAsync(mu, st);
     hipFreeAsync(xnorm, st);
-    hipFreeAsync(qnorm, st);
     hipFreeAsync(cand, st);
     hipFreeAsync(cbuf, st);
     if (e != hipSuccess) return fail(NSG_EDEVICE, "brute-force launch failed: %s", hipGetErrorString(e));

@@ -26,7 +26,8 @@ def nsg():
 
 
 @pytest.mark.parametrize("n,d,nq,k", [(10_000, 128, 100, 100), (3_001, 37, 70, 10), (500, 960, 9, 5),
-                                      (77, 16, 5, 100)])
+                                      (77, 16, 5, 100), (3_001, 129, 70, 10), (1_500, 200, 300, 100),
+                                      (700, 1024, 130, 160)])
 def test_bruteforce_matches_exact_knn(nsg, n, d, nq, k):
     dev = _dev()
     rng = np.random.default_rng(n + d)
@@ -44,6 +45,22 @@ def test_bruteforce_matches_exact_knn(nsg, n, d, nq, k):
     dd = np.where(fin, dd, np.float32(3e38))
     assert (np.diff(dd, axis=1) >= 0).all()
     assert ((ids.cpu().numpy() == -1) == ~fin).all()
+
+
+@pytest.mark.parametrize("n,d,k", [(2_000, 96, 40), (1_300, 300, 25)])
+def test_bruteforce_knn_graph_excludes_self(nsg, n, d, k):
+    """kNN graph (queries = base rows, own row excluded) on both stage-1
+    kernels (d <= 128 and d > 128) against the FP64 oracle."""
+    dev = _dev()
+    rng = np.random.default_rng(n * d)
+    X = (rng.normal(size=(n, d)) * 20 + 100).astype(np.float32)
+    Xd = torch.from_numpy(X).to(dev)
+    ids, dist = nsg.knn_bruteforce(Xd, Xd, k, exclude_self=True)
+    ids = ids.cpu().numpy().view(np.uint32)
+    assert not (ids == np.arange(n)[:, None]).any()
+    o_ids, _ = oracle.knn(X, X, k, exclude_self=True)
+    r = compare(X, X, ids, dist.cpu().numpy(), o_ids, rtol=1e-5, min_match=1.0)
+    assert r["ok"], {kk: v for kk, v in r.items() if kk != "bad"}
 
 
 def test_bruteforce_knn_graph_tiny(nsg, tiny_index):
