@@ -164,9 +164,23 @@ __device__ __attribute__((noinline)) uint32_t wave_keep_smallest(uint64_t *buf, 
         ok[e] = j < c;
         key[e] = ok[e] ? buf[j] : 0ull;
     }
-    uint32_t prefix = 0u;
+    // bits on which every key agrees are the target's too: start below them
+    uint32_t all_or = 0u, all_and = 0xFFFFFFFFu;
+#pragma unroll
+    for (int e = 0; e < M; ++e) {
+        const uint32_t h = (uint32_t)(key[e] >> 32);
+        all_or |= ok[e] ? h : 0u;
+        all_and &= ok[e] ? h : 0xFFFFFFFFu;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        all_or |= (uint32_t)__shfl_xor((int)all_or, o);
+        all_and &= (uint32_t)__shfl_xor((int)all_and, o);
+    }
+    const uint32_t diff = all_or ^ all_and;
+    const int top = diff ? 31 - __builtin_clz(diff) : -1;   // highest bit on which keys differ
+    uint32_t prefix = top >= 31 ? 0u : (all_and & (0xFFFFFFFFu << (top + 1)));
     int need = Kp;   // rank of the target among the entries that match the prefix so far
-    for (int b = 31; b >= 0; --b) {
+    for (int b = top; b >= 0; --b) {
         const uint32_t above = b == 31 ? 0u : (0xFFFFFFFFu << (b + 1));
         int cnt = 0;
 #pragma unroll
@@ -742,15 +756,12 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     if (!base || !queries || !out_ids || !out_dist) return fail(NSG_EINVAL, "NULL pointer");
     if (exclude_self && nq > n) return fail(NSG_EINVAL, "exclude_self needs queries = base rows");
     hipStream_t st = (hipStream_t)stream;
-    // over-fetch margin 24 for the inner-product form's rounding; buffer of
-    // Kp + two tiles (next power of two)
+    // over-fetch margin 24 for the inner-product form's rounding
     const int Kp = (k + 24 + 31) / 32 * 32;
     // d <= 128: wide query tiles (4 waves x kWideQW queries, 64-row tiles);
     // d > 128: chunked dimensions (4 waves x 32 queries, 128-row tiles)
     const bool wide = d <= 128;
     const int tile = wide ? BX : CX;
-    int cap = 1;
-    while (cap < Kp + 2 * tile) cap <<= 1;
     const bool vec4 = d % 4 == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0 &&
                       (reinterpret_cast<uintptr_t>(queries) & 15) == 0;
     const int bq = wide ? 4 * kWideQW : CQ;
@@ -777,6 +788,11 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     int64_t split_len = (n + nsplit - 1) / nsplit;
     split_len = (split_len + BX - 1) / BX * BX;
     nsplit = (int)((n + split_len - 1) / split_len);
+    // candidate buffers: Kp + two tiles at least; 512 (what a cut handles)
+    // while all of them stay within 8 GiB, so that a cut absorbs more appends
+    int cap = 1;
+    while (cap < Kp + 2 * tile) cap <<= 1;
+    if ((double)qtiles * nsplit * bq * 512 * sizeof(uint64_t) <= 8.0 * (1 << 30)) cap = 512;
     const int ncand = nsplit * Kp;
     int sort_n = 1;
     while (sort_n < ncand) sort_n <<= 1;
