@@ -27,7 +27,7 @@ def nsg():
 
 @pytest.mark.parametrize("n,d,nq,k", [(10_000, 128, 100, 100), (3_001, 37, 70, 10), (500, 960, 9, 5),
                                       (77, 16, 5, 100), (3_001, 129, 70, 10), (1_500, 200, 300, 100),
-                                      (700, 1024, 130, 160)])
+                                      (700, 1024, 130, 160), (50, 300, 7, 100)])
 def test_bruteforce_matches_exact_knn(nsg, n, d, nq, k):
     dev = _dev()
     rng = np.random.default_rng(n + d)
