@@ -105,8 +105,8 @@ __device__ inline uint64_t bkey(float d, uint32_t id) {
     return ((uint64_t)__float_as_uint(d) << 32) | id;
 }
 
-// sort buf[0..cnt) ascending (padded to cap with +inf), keep the first Kp.
-// Executed by one wave.
+// Sort buf[0..cnt) ascending in place (bitonic, padded with ~0 up to the next
+// power of two, at most cap).  Executed by one wave.
 __device__ inline void wave_sort_buf(uint64_t *buf, int cnt, int cap, int lane) {
     int np = 1;
     while (np < cnt) np <<= 1;
