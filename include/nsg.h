@@ -273,8 +273,11 @@ int nsg_autotune(const nsg_index *idx, const float *queries, int64_t nq, int32_t
  * distance minus a per-query constant), over-fetched, then re-ranked with exact FP32
  * differences (sum of (q_j - x_j)^2).  exclude_self != 0: queries are the base
  * rows themselves and query i never returns row i (kNN graph).  base[n][d],
- * queries[nq][d] FP32; out_ids / out_dist [nq][k].  1 <= k <= 160.  Scratch
- * memory is allocated and freed on `stream` (stream-ordered allocations).
+ * queries[nq][d] FP32; out_ids / out_dist [nq][k].  1 <= k <= 160, 1 <= d <=
+ * 65536.  Scratch memory is allocated and freed on `stream` (stream-ordered
+ * allocations): candidate buffers of 512 keys (8 bytes each) per query and
+ * base split while they total at most 8 GiB (fewer keys per query above
+ * that), plus O(n + nq * k) words.  Returns NSG_ENOMEM if an allocation fails.
  */
 int nsg_knn_bruteforce(const float *base, int64_t n, const float *queries,
                        int64_t nq, int32_t d, int32_t k, int32_t exclude_self,

@@ -801,12 +801,27 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     float2 *acc = nullptr;
     uint32_t *cand = nullptr;
     uint64_t *cbuf = nullptr;
-    NSG_HIP(hipMallocAsync((void **)&acc, sizeof(float2) * d * mean_blocks(n), st));
-    NSG_HIP(hipMallocAsync((void **)&mu, sizeof(float) * d, st));
-    NSG_HIP(hipMallocAsync((void **)&xnorm, sizeof(float) * n, st));
-    NSG_HIP(hipMallocAsync((void **)&cand, sizeof(uint32_t) * nq * ncand, st));
-    NSG_HIP(hipMallocAsync((void **)&cbuf, sizeof(uint64_t) * qtiles * nsplit * bq * cap, st));
-    if (int rc = launch_mean(base, n, d, mu, acc, st)) return rc;
+    // stream-ordered scratch, released on every exit
+    auto release = [&]() {
+        if (acc) hipFreeAsync(acc, st);
+        if (mu) hipFreeAsync(mu, st);
+        if (xnorm) hipFreeAsync(xnorm, st);
+        if (cand) hipFreeAsync(cand, st);
+        if (cbuf) hipFreeAsync(cbuf, st);
+    };
+    const size_t cbuf_bytes = sizeof(uint64_t) * qtiles * nsplit * bq * cap;
+    if (hipMallocAsync((void **)&acc, sizeof(float2) * d * mean_blocks(n), st) != hipSuccess ||
+        hipMallocAsync((void **)&mu, sizeof(float) * d, st) != hipSuccess ||
+        hipMallocAsync((void **)&xnorm, sizeof(float) * n, st) != hipSuccess ||
+        hipMallocAsync((void **)&cand, sizeof(uint32_t) * nq * ncand, st) != hipSuccess ||
+        hipMallocAsync((void **)&cbuf, cbuf_bytes, st) != hipSuccess) {
+        release();
+        return fail(NSG_ENOMEM, "brute-force scratch allocation failed (%zu bytes of candidate buffers)", cbuf_bytes);
+    }
+    if (int rc = launch_mean(base, n, d, mu, acc, st)) {
+        release();
+        return rc;
+    }
     hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, d, mu, xnorm);
     BFParams p{};
     p.base = base;
@@ -833,11 +848,7 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
                            out_dist);
     }
     hipError_t e = le != hipSuccess ? le : hipGetLastError();
-    hipFreeAsync(acc, st);
-    hipFreeAsync(mu, st);
-    hipFreeAsync(xnorm, st);
-    hipFreeAsync(cand, st);
-    hipFreeAsync(cbuf, st);
+    release();
     if (e != hipSuccess) return fail(NSG_EDEVICE, "brute-force launch failed: %s", hipGetErrorString(e));
     return NSG_OK;
 }
