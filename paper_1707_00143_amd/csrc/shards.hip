@@ -202,8 +202,11 @@ extern "C" int nsg_search_shards(const nsg_shards *sh, const float *queries, int
     const int64_t T = nq * sh->S;
     uint32_t *sid = nullptr;
     float *sd = nullptr;
-    NSG_HIP(hipMallocAsync((void **)&sid, sizeof(uint32_t) * T * k, st));
-    NSG_HIP(hipMallocAsync((void **)&sd, sizeof(float) * T * k, st));
+    if (hipMallocAsync((void **)&sid, sizeof(uint32_t) * T * k, st) != hipSuccess ||
+        hipMallocAsync((void **)&sd, sizeof(float) * T * k, st) != hipSuccess) {
+        if (sid) hipFreeAsync(sid, st);
+        return fail(NSG_ENOMEM, "per-subset result allocation failed");
+    }
     SearchArgs a{};
     a.idx = sh->ix;
     a.queries = queries;
