@@ -222,32 +222,64 @@ extern "C" int nsg_knn_ivf(const float *base, int64_t n, int32_t d, const uint32
         mmax = std::max(mmax, hc[c]);
         qmax = std::max(qmax, hc[nlist + c]);
     }
-    // 3. cell by cell: probing points against members, merged into the lists
+    // 3. cell by cell: probing points against members, merged into the lists.
+    // Consecutive cells alternate between the caller's stream and a second
+    // one, each with its own row and result buffers, so that a cell's gathers
+    // and brute force overlap the previous cell's; the merges, which update
+    // the shared per-point lists, keep the cell order through events.
     const int kc = K + 1;
-    float *bbuf = nullptr, *qbuf = nullptr, *cd = nullptr;
-    uint32_t *ci = nullptr;
-    if ((rc = dalloc((void **)&bbuf, sizeof(float) * (size_t)mmax * d)) ||
-        (rc = dalloc((void **)&qbuf, sizeof(float) * (size_t)qmax * d)) ||
-        (rc = dalloc((void **)&ci, sizeof(uint32_t) * (size_t)qmax * kc)) ||
-        (rc = dalloc((void **)&cd, sizeof(float) * (size_t)qmax * kc)))
-        return rc;
+    float *bbuf[2] = {nullptr, nullptr}, *qbuf[2] = {nullptr, nullptr}, *cd[2] = {nullptr, nullptr};
+    uint32_t *ci[2] = {nullptr, nullptr};
+    for (int h = 0; h < 2; ++h)
+        if ((rc = dalloc((void **)&bbuf[h], sizeof(float) * (size_t)mmax * d)) ||
+            (rc = dalloc((void **)&qbuf[h], sizeof(float) * (size_t)qmax * d)) ||
+            (rc = dalloc((void **)&ci[h], sizeof(uint32_t) * (size_t)qmax * kc)) ||
+            (rc = dalloc((void **)&cd[h], sizeof(float) * (size_t)qmax * kc)))
+            return rc;
+    struct Side {
+        hipStream_t s2 = nullptr;
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        ~Side() {
+            if (s2) {
+                hipStreamSynchronize(s2);
+                hipStreamDestroy(s2);
+            }
+            for (hipEvent_t e : ev)
+                if (e) hipEventDestroy(e);
+        }
+    } side;
+    NSG_HIP(hipStreamCreateWithFlags(&side.s2, hipStreamNonBlocking));
+    for (hipEvent_t &e : side.ev) NSG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // the second stream starts after the set-up above
+    NSG_HIP(hipEventRecord(side.ev[2], st));
+    NSG_HIP(hipStreamWaitEvent(side.s2, side.ev[2], 0));
     const int wpb = 4;
     const size_t lds = (size_t)wpb * (2 * K + 2) * 8;
-    int64_t moff = 0, qoff = 0;
+    int64_t moff = 0, qoff = 0, done = 0;
     for (int c = 0; c < nlist; ++c) {
         const int64_t m = hc[c], q = hc[nlist + c];
         if (m > 0 && q > 0) {
-            hipLaunchKernelGGL(ivf_gather_kernel, dim3((unsigned)m), dim3(128), 0, st, base, d, member + moff, bbuf);
-            hipLaunchKernelGGL(ivf_gather_kernel, dim3((unsigned)q), dim3(128), 0, st, base, d, qmember + qoff, qbuf);
+            const int h = (int)(done & 1);
+            hipStream_t s = h ? side.s2 : st;
+            hipLaunchKernelGGL(ivf_gather_kernel, dim3((unsigned)m), dim3(128), 0, s, base, d, member + moff,
+                               bbuf[h]);
+            hipLaunchKernelGGL(ivf_gather_kernel, dim3((unsigned)q), dim3(128), 0, s, base, d, qmember + qoff,
+                               qbuf[h]);
             NSG_HIP(hipGetLastError());
-            if ((rc = nsg_knn_bruteforce(bbuf, m, qbuf, q, d, kc, 0, ci, cd, stream))) return rc;
-            hipLaunchKernelGGL(ivf_merge_kernel, dim3((unsigned)((q + wpb - 1) / wpb)), dim3(64 * wpb), lds, st,
-                               qmember + qoff, q, member + moff, ci, cd, kc, lists, (int)K);
+            if ((rc = nsg_knn_bruteforce(bbuf[h], m, qbuf[h], q, d, kc, 0, ci[h], cd[h], s))) return rc;
+            // merges in cell order: after the previous cell's (other stream)
+            if (done > 0) NSG_HIP(hipStreamWaitEvent(s, side.ev[h ^ 1], 0));
+            hipLaunchKernelGGL(ivf_merge_kernel, dim3((unsigned)((q + wpb - 1) / wpb)), dim3(64 * wpb), lds, s,
+                               qmember + qoff, q, member + moff, ci[h], cd[h], kc, lists, (int)K);
             NSG_HIP(hipGetLastError());
+            NSG_HIP(hipEventRecord(side.ev[h], s));
+            ++done;
         }
         moff += m;
         qoff += q;
     }
+    // the caller's stream continues after the last merge
+    if (done > 0) NSG_HIP(hipStreamWaitEvent(st, side.ev[(done - 1) & 1], 0));
     hipLaunchKernelGGL(ivf_out_kernel, dim3(grid_of(n * K)), dim3(256), 0, st, lists, n * (int64_t)K, out_ids,
                        out_dist);
     NSG_HIP(hipGetLastError());
