@@ -31,6 +31,7 @@ namespace nsg {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BX = 64;   // rows per base tile of the wide kernel
+constexpr int kCutSlack = 32;   // an intermediate cut keeps at most Kp + 32 keys
 
 struct BFParams {
     const float *base, *queries;
@@ -147,14 +148,22 @@ __device__ inline void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Keep the Kp entries of buf[0..c) with the smallest rank values (the high
-// words of the keys; ties at the cut taken in buffer order) in buf[0..Kp),
-// in no particular order, and return the Kp-th smallest high word.  c in
-// [Kp, 512].  One wave: the high word of the Kp-th smallest is found bit by
-// bit from the top (a radix select counting with ballots), then the kept
-// entries are written to the front.  Every load precedes every store (the
-// stores depend on ballots over all loaded keys).
-__device__ __attribute__((noinline)) uint32_t wave_keep_smallest(uint64_t *buf, int c, int Kp, int lane) {
+// Cut buf[0..c) (c in [Kp, 512]) to at least its Kp entries with the
+// smallest rank values (the high words of the keys), moved to the front in no
+// particular order, and return the bound B such that every kept entry and no
+// dropped one has a high word below B (2^32: no bound); *kept receives their
+// number.  slack = 0: exactly Kp are kept (ties at the cut taken in buffer
+// order: then B is the Kp-th smallest high word and the tied ones beyond Kp
+// are dropped, none of them below B).  slack > 0: at most Kp + slack (an
+// intermediate cut needs no exact count: rejecting later values at or above
+// B keeps every entry that can still be among the Kp best).  One wave: the
+// bucket of high words holding the Kp-th smallest is narrowed bit by bit from
+// the highest bit on which the keys differ (a radix select counting with
+// ballots); with slack it stops once the bucket and everything below it hold
+// at most Kp + slack entries.  Every load precedes every store (the stores
+// depend on ballots over all loaded keys).
+__device__ __attribute__((noinline)) uint64_t wave_keep_smallest(uint64_t *buf, int c, int Kp, int slack, int lane,
+                                                                 int *kept) {
     constexpr int M = 8;
     uint64_t key[M];
     bool ok[M];
@@ -179,30 +188,39 @@ __device__ __attribute__((noinline)) uint32_t wave_keep_smallest(uint64_t *buf, 
     const uint32_t diff = all_or ^ all_and;
     const int top = diff ? 31 - __builtin_clz(diff) : -1;   // highest bit on which keys differ
     uint32_t prefix = top >= 31 ? 0u : (all_and & (0xFFFFFFFFu << (top + 1)));
-    int need = Kp;   // rank of the target among the entries that match the prefix so far
+    int need = Kp;      // rank of the target among the entries in the bucket
+    int in_bucket = c;  // entries whose high word matches the prefix on the bits examined
+    uint64_t bound = 0; // > 0: early stop, keep every entry below it
     for (int b = top; b >= 0; --b) {
         const uint32_t above = b == 31 ? 0u : (0xFFFFFFFFu << (b + 1));
         int cnt = 0;
 #pragma unroll
         for (int e = 0; e < M; ++e) {
-            if (e * 64 >= c) break;
             const uint32_t h = (uint32_t)(key[e] >> 32);
-            cnt += __popcll(__ballot(ok[e] && (h & above) == prefix && ((h >> b) & 1u) == 0u));
+            if (e * 64 < c) cnt += __popcll(__ballot(ok[e] && (h & above) == prefix && ((h >> b) & 1u) == 0u));
         }
         if (cnt < need) {
             need -= cnt;
+            in_bucket -= cnt;
             prefix |= 1u << b;
+        } else {
+            in_bucket = cnt;
+        }
+        if (slack > 0 && in_bucket - need <= slack) {   // bucket [prefix, prefix + 2^b) and all below it
+            bound = (uint64_t)prefix + (1ull << b);
+            break;
         }
     }
-    // entries below the prefix value go to [0, Kp - need), the first `need`
-    // equal to it to [Kp - need, Kp)
+    // bound: entries below it to the front; else entries below the prefix
+    // value to [0, Kp - need), the first `need` equal to it to [Kp - need, Kp)
     const uint64_t below = (1ull << lane) - 1ull;
     int at_lt = 0, at_eq = Kp - need, eq_seen = 0;
 #pragma unroll
     for (int e = 0; e < M; ++e) {
-        if (e * 64 >= c) break;
+        if (e * 64 >= c) continue;
         const uint32_t h = (uint32_t)(key[e] >> 32);
-        const bool lt = ok[e] && h < prefix, eq = ok[e] && h == prefix;
+        const bool lt = ok[e] && (bound ? (uint64_t)h < bound : h < prefix);
+        const bool eq = !bound && ok[e] && h == prefix;
         const uint64_t blt = __ballot(lt), beq = __ballot(eq);
         const int rl = __popcll(blt & below), re = __popcll(beq & below);
         if (lt) buf[at_lt + rl] = key[e];
@@ -210,7 +228,14 @@ __device__ __attribute__((noinline)) uint32_t wave_keep_smallest(uint64_t *buf, 
         at_lt += __popcll(blt);
         eq_seen += __popcll(beq);
     }
-    return prefix;
+    *kept = bound ? at_lt : Kp;
+    return bound ? bound : (uint64_t)prefix;
+}
+
+// the rank-value threshold for a cut's bound B: later values v are appended
+// only while ord_bits(v) < B
+__device__ inline float cut_threshold(uint64_t B) {
+    return B > 0xFF800000ull ? INFINITY : ord_float((uint32_t)B);
 }
 
 // Stage 1 for d <= 128 with wide query tiles.  Every wave owns QW queries
@@ -412,10 +437,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
                 const int r = __builtin_ctzll(full);
                 full &= full - 1;
                 const int c = cnt_w[r];
-                const float tnew = ord_float(wave_keep_smallest(buf + (size_t)r * p.cap, c, p.Kp, lane));
+                int kept = 0;
+                const float tnew = cut_threshold(wave_keep_smallest(buf + (size_t)r * p.cap, c, p.Kp, kCutSlack,
+                                                                    lane, &kept));
                 wave_fence();
                 if (lane == 0) {
-                    cnt_w[r] = p.Kp;
+                    cnt_w[r] = kept;
                     thr_w[r] = tnew;
                 }
                 wave_fence();
@@ -434,7 +461,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
         const int c = cnt_w[r];
         uint64_t *br = buf + (size_t)r * p.cap;
         if (c > p.Kp) {
-            wave_keep_smallest(br, c, p.Kp, lane);
+            int kept = 0;
+            wave_keep_smallest(br, c, p.Kp, 0, lane, &kept);
             wave_fence();
         }
         uint32_t *dst = p.cand_ids + (qi * p.nsplit + split) * (int64_t)p.Kp;
@@ -643,10 +671,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
                 const int r = __builtin_ctzll(full);
                 full &= full - 1;
                 const int c = cnt_w[r];
-                const float tnew = ord_float(wave_keep_smallest(buf + (size_t)r * p.cap, c, p.Kp, lane));
+                int kept = 0;
+                const float tnew = cut_threshold(wave_keep_smallest(buf + (size_t)r * p.cap, c, p.Kp, kCutSlack,
+                                                                    lane, &kept));
                 wave_fence();
                 if (lane == 0) {
-                    cnt_w[r] = p.Kp;
+                    cnt_w[r] = kept;
                     thr_w[r] = tnew;
                 }
                 wave_fence();
@@ -661,7 +691,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
         const int c = cnt_w[r];
         uint64_t *br = buf + (size_t)r * p.cap;
         if (c > p.Kp) {
-            wave_keep_smallest(br, c, p.Kp, lane);
+            int kept = 0;
+            wave_keep_smallest(br, c, p.Kp, 0, lane, &kept);
             wave_fence();
         }
         uint32_t *dst = p.cand_ids + (qi * p.nsplit + split) * (int64_t)p.Kp;
