@@ -76,7 +76,19 @@ __global__ void mean_finish_kernel(const float2 *part, int nblk, int64_t n, int 
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= d) return;
     float s = 0.0f, c = 0.0f;
-    for (int b = 0; b < nblk; ++b) {
+    constexpr int U = 16;   // partials loaded together, then added in block order
+    int b = 0;
+    for (; b + U <= nblk; b += U) {
+        float2 p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) p[u] = part[(size_t)(b + u) * d + j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            neumaier_add(s, c, p[u].x);
+            c += p[u].y;
+        }
+    }
+    for (; b < nblk; ++b) {
         const float2 p = part[(size_t)b * d + j];
         neumaier_add(s, c, p.x);
         c += p.y;
@@ -771,6 +783,131 @@ WideKernel wide_kernel_v(int d) {
                       : wide_kernel_t<128, VEC>();
 }
 
+// Launch plan of one brute force: stage-1 kernel, splits of the base,
+// candidate counts, and the offsets of its scratch in one block of memory.
+struct BFPlan {
+    WideKernel wk;
+    int Kp, cap, nsplit, ncand, sort_n;
+    int64_t qtiles, split_len;
+    size_t off_mu, off_xnorm, off_cand, off_cbuf, bytes;
+};
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// arguments are validated by the caller
+static int bf_plan(const float *base, int64_t n, const float *queries, int64_t nq, int d, int k, BFPlan *pl) {
+    BFPlan &P = *pl;
+    // over-fetch margin 24 for the inner-product form's rounding
+    P.Kp = (k + 24 + 31) / 32 * 32;
+    // d <= 128: wide query tiles (4 waves x kWideQW queries, 64-row tiles);
+    // d > 128: chunked dimensions (4 waves x 32 queries, 128-row tiles)
+    const bool wide = d <= 128;
+    const int tile = wide ? BX : CX;
+    const bool vec4 = d % 4 == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(queries) & 15) == 0;
+    const int bq = wide ? 4 * kWideQW : CQ;
+    P.qtiles = (nq + bq - 1) / bq;
+    if (wide) {
+        P.wk = vec4 ? wide_kernel_v<true>(d) : wide_kernel_v<false>(d);
+    } else {
+        const size_t lds = (size_t)4 * CQ * CLD * 4 + (size_t)8 * 32 * 4;
+        P.wk = {vec4 ? (const void *)bf_chunked_kernel<true> : (const void *)bf_chunked_kernel<false>, lds};
+    }
+    // splits of the base: with fewer query tiles than resident blocks, enough
+    // splits for one full round of blocks (fewer splits keep the exact pass
+    // short); at least a few tiles per split
+    NSG_HIP(hipFuncSetAttribute(P.wk.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.wk.lds));
+    int dev = 0, cus = 0, per_cu = 0;
+    NSG_HIP(hipGetDevice(&dev));
+    NSG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    NSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, P.wk.fn, 256, P.wk.lds));
+    const int64_t slots = std::max<int64_t>(1, (int64_t)cus * per_cu);
+    const int64_t want = std::max<int64_t>(1, slots / P.qtiles);
+    const int64_t max_split = std::max<int64_t>(1, n / (BX * 8));
+    P.nsplit = (int)std::min<int64_t>(std::min<int64_t>(want, max_split), std::max(1, 4096 / P.Kp));
+    P.split_len = (n + P.nsplit - 1) / P.nsplit;
+    P.split_len = (P.split_len + BX - 1) / BX * BX;
+    P.nsplit = (int)((n + P.split_len - 1) / P.split_len);
+    // candidate buffers: Kp + two tiles at least; 512 (what a cut handles)
+    // while all of them stay within 8 GiB, so that a cut absorbs more appends
+    P.cap = 1;
+    while (P.cap < P.Kp + 2 * tile) P.cap <<= 1;
+    if ((double)P.qtiles * P.nsplit * bq * 512 * sizeof(uint64_t) <= 8.0 * (1 << 30)) P.cap = 512;
+    P.ncand = P.nsplit * P.Kp;
+    P.sort_n = 1;
+    while (P.sort_n < P.ncand) P.sort_n <<= 1;
+    if (P.sort_n * 8 > 64 * 1024) return fail(NSG_EUNSUPPORTED, "too many candidates per query (%d)", P.ncand);
+    // scratch: column partial sums, mean, centred row norms, candidate ids,
+    // candidate buffers; each 256-byte aligned
+    P.off_mu = align256(sizeof(float2) * d * mean_blocks(n));
+    P.off_xnorm = P.off_mu + align256(sizeof(float) * d);
+    P.off_cand = P.off_xnorm + align256(sizeof(float) * n);
+    P.off_cbuf = P.off_cand + align256(sizeof(uint32_t) * nq * P.ncand);
+    P.bytes = P.off_cbuf + align256(sizeof(uint64_t) * P.qtiles * P.nsplit * bq * P.cap);
+    return NSG_OK;
+}
+
+static int bf_launch(const BFPlan &P, const float *base, int64_t n, const float *queries, int64_t nq, int d, int k,
+                     int exclude_self, uint32_t *out_ids, float *out_dist, unsigned char *ws, hipStream_t st) {
+    float2 *acc = reinterpret_cast<float2 *>(ws);
+    float *mu = reinterpret_cast<float *>(ws + P.off_mu);
+    float *xnorm = reinterpret_cast<float *>(ws + P.off_xnorm);
+    uint32_t *cand = reinterpret_cast<uint32_t *>(ws + P.off_cand);
+    uint64_t *cbuf = reinterpret_cast<uint64_t *>(ws + P.off_cbuf);
+    if (int rc = launch_mean(base, n, d, mu, acc, st)) return rc;
+    hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, d, mu, xnorm);
+    BFParams p{};
+    p.base = base;
+    p.queries = queries;
+    p.mu = mu;
+    p.xnorm = xnorm;
+    p.n = n;
+    p.nq = nq;
+    p.d = d;
+    p.Kp = P.Kp;
+    p.cap = P.cap;
+    p.split_len = P.split_len;
+    p.nsplit = P.nsplit;
+    p.exclude_self = exclude_self ? 1 : 0;
+    p.cand_ids = cand;
+    p.cand_buf = cbuf;
+    void *args[] = {&p};
+    const hipError_t le =
+        hipLaunchKernel(P.wk.fn, dim3((unsigned)P.qtiles, (unsigned)P.nsplit), dim3(256), args, P.wk.lds, st);
+    // stage 2 reads the candidates stage 1 wrote: launched only after it
+    if (le == hipSuccess) {
+        const int wpb = std::max(1, std::min(4, (int)(64 * 1024 / ((size_t)P.sort_n * 8))));
+        hipLaunchKernelGGL(bf_rerank_kernel, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb),
+                           (size_t)P.sort_n * 8 * wpb, st, base, queries, nq, d, cand, P.ncand, k, P.sort_n, out_ids,
+                           out_dist);
+    }
+    const hipError_t e = le != hipSuccess ? le : hipGetLastError();
+    if (e != hipSuccess) return fail(NSG_EDEVICE, "brute-force launch failed: %s", hipGetErrorString(e));
+    return NSG_OK;
+}
+
+// For callers that run many brute forces back to back (the inverted-file
+// graph): the scratch one call takes, and the call on scratch the caller
+// owns (256-byte aligned, at least that many bytes, not used by another
+// call in flight).  Arguments as nsg_knn_bruteforce's, validated by the
+// caller.
+int bf_scratch_bytes(const float *base, int64_t n, const float *queries, int64_t nq, int d, int k, size_t *bytes) {
+    BFPlan P{};
+    if (int rc = bf_plan(base, n, queries, nq, d, k, &P)) return rc;
+    *bytes = P.bytes;
+    return NSG_OK;
+}
+
+int bf_with_scratch(const float *base, int64_t n, const float *queries, int64_t nq, int d, int k, int exclude_self,
+                    uint32_t *out_ids, float *out_dist, void *scratch, size_t scratch_bytes, hipStream_t st) {
+    BFPlan P{};
+    if (int rc = bf_plan(base, n, queries, nq, d, k, &P)) return rc;
+    if (P.bytes > scratch_bytes)
+        return fail(NSG_EINVAL, "brute-force scratch of %zu bytes, %zu needed", scratch_bytes, P.bytes);
+    return bf_launch(P, base, n, queries, nq, d, k, exclude_self, out_ids, out_dist,
+                     static_cast<unsigned char *>(scratch), st);
+}
+
 }  // namespace nsg
 
 using namespace nsg;
@@ -787,99 +924,13 @@ extern "C" int nsg_knn_bruteforce(const float *base, int64_t n, const float *que
     if (!base || !queries || !out_ids || !out_dist) return fail(NSG_EINVAL, "NULL pointer");
     if (exclude_self && nq > n) return fail(NSG_EINVAL, "exclude_self needs queries = base rows");
     hipStream_t st = (hipStream_t)stream;
-    // over-fetch margin 24 for the inner-product form's rounding
-    const int Kp = (k + 24 + 31) / 32 * 32;
-    // d <= 128: wide query tiles (4 waves x kWideQW queries, 64-row tiles);
-    // d > 128: chunked dimensions (4 waves x 32 queries, 128-row tiles)
-    const bool wide = d <= 128;
-    const int tile = wide ? BX : CX;
-    const bool vec4 = d % 4 == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0 &&
-                      (reinterpret_cast<uintptr_t>(queries) & 15) == 0;
-    const int bq = wide ? 4 * kWideQW : CQ;
-    const int64_t qtiles = (nq + bq - 1) / bq;
-    // splits of the base: with fewer query tiles than resident blocks, enough
-    // splits for one full round of blocks (fewer splits keep the exact pass
-    // short); at least a few tiles per split
-    WideKernel wk{};
-    if (wide) {
-        wk = vec4 ? wide_kernel_v<true>(d) : wide_kernel_v<false>(d);
-    } else {
-        const size_t lds = (size_t)4 * CQ * CLD * 4 + (size_t)8 * 32 * 4;
-        wk = {vec4 ? (const void *)bf_chunked_kernel<true> : (const void *)bf_chunked_kernel<false>, lds};
-    }
-    NSG_HIP(hipFuncSetAttribute(wk.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wk.lds));
-    int dev = 0, cus = 0, per_cu = 0;
-    NSG_HIP(hipGetDevice(&dev));
-    NSG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    NSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wk.fn, 256, wk.lds));
-    const int64_t slots = std::max<int64_t>(1, (int64_t)cus * per_cu);
-    const int64_t want = std::max<int64_t>(1, slots / qtiles);
-    int64_t max_split = std::max<int64_t>(1, n / (BX * 8));
-    int nsplit = (int)std::min<int64_t>(std::min<int64_t>(want, max_split), std::max(1, 4096 / Kp));
-    int64_t split_len = (n + nsplit - 1) / nsplit;
-    split_len = (split_len + BX - 1) / BX * BX;
-    nsplit = (int)((n + split_len - 1) / split_len);
-    // candidate buffers: Kp + two tiles at least; 512 (what a cut handles)
-    // while all of them stay within 8 GiB, so that a cut absorbs more appends
-    int cap = 1;
-    while (cap < Kp + 2 * tile) cap <<= 1;
-    if ((double)qtiles * nsplit * bq * 512 * sizeof(uint64_t) <= 8.0 * (1 << 30)) cap = 512;
-    const int ncand = nsplit * Kp;
-    int sort_n = 1;
-    while (sort_n < ncand) sort_n <<= 1;
-    if (sort_n * 8 > 64 * 1024) return fail(NSG_EUNSUPPORTED, "too many candidates per query (%d)", ncand);
-    float *mu = nullptr, *xnorm = nullptr;
-    float2 *acc = nullptr;
-    uint32_t *cand = nullptr;
-    uint64_t *cbuf = nullptr;
+    BFPlan P{};
+    if (int rc = bf_plan(base, n, queries, nq, d, k, &P)) return rc;
     // stream-ordered scratch, released on every exit
-    auto release = [&]() {
-        if (acc) hipFreeAsync(acc, st);
-        if (mu) hipFreeAsync(mu, st);
-        if (xnorm) hipFreeAsync(xnorm, st);
-        if (cand) hipFreeAsync(cand, st);
-        if (cbuf) hipFreeAsync(cbuf, st);
-    };
-    const size_t cbuf_bytes = sizeof(uint64_t) * qtiles * nsplit * bq * cap;
-    if (hipMallocAsync((void **)&acc, sizeof(float2) * d * mean_blocks(n), st) != hipSuccess ||
-        hipMallocAsync((void **)&mu, sizeof(float) * d, st) != hipSuccess ||
-        hipMallocAsync((void **)&xnorm, sizeof(float) * n, st) != hipSuccess ||
-        hipMallocAsync((void **)&cand, sizeof(uint32_t) * nq * ncand, st) != hipSuccess ||
-        hipMallocAsync((void **)&cbuf, cbuf_bytes, st) != hipSuccess) {
-        release();
-        return fail(NSG_ENOMEM, "brute-force scratch allocation failed (%zu bytes of candidate buffers)", cbuf_bytes);
-    }
-    if (int rc = launch_mean(base, n, d, mu, acc, st)) {
-        release();
-        return rc;
-    }
-    hipLaunchKernelGGL(cnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, d, mu, xnorm);
-    BFParams p{};
-    p.base = base;
-    p.queries = queries;
-    p.mu = mu;
-    p.xnorm = xnorm;
-    p.n = n;
-    p.nq = nq;
-    p.d = d;
-    p.Kp = Kp;
-    p.cap = cap;
-    p.split_len = split_len;
-    p.nsplit = nsplit;
-    p.exclude_self = exclude_self ? 1 : 0;
-    p.cand_ids = cand;
-    p.cand_buf = cbuf;
-    void *args[] = {&p};
-    const hipError_t le = hipLaunchKernel(wk.fn, dim3((unsigned)qtiles, (unsigned)nsplit), dim3(256), args, wk.lds, st);
-    // stage 2 reads the candidates stage 1 wrote: launched only after it
-    if (le == hipSuccess) {
-        const int wpb = std::max(1, std::min(4, (int)(64 * 1024 / ((size_t)sort_n * 8))));
-        hipLaunchKernelGGL(bf_rerank_kernel, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb),
-                           (size_t)sort_n * 8 * wpb, st, base, queries, nq, d, cand, ncand, k, sort_n, out_ids,
-                           out_dist);
-    }
-    hipError_t e = le != hipSuccess ? le : hipGetLastError();
-    release();
-    if (e != hipSuccess) return fail(NSG_EDEVICE, "brute-force launch failed: %s", hipGetErrorString(e));
-    return NSG_OK;
+    unsigned char *ws = nullptr;
+    if (hipMallocAsync((void **)&ws, P.bytes, st) != hipSuccess)
+        return fail(NSG_ENOMEM, "brute-force scratch allocation of %zu bytes failed", P.bytes);
+    const int rc = bf_launch(P, base, n, queries, nq, d, k, exclude_self, out_ids, out_dist, ws, st);
+    hipFreeAsync(ws, st);
+    return rc;
 }

@@ -22,6 +22,14 @@
 #include <vector>
 
 namespace nsg {
+// the brute force on scratch the caller owns (defined beside
+// nsg_knn_bruteforce): its scratch bytes for these operands, and the call
+int bf_scratch_bytes(const float *base, int64_t n, const float *queries, int64_t nq, int d, int k, size_t *bytes);
+int bf_with_scratch(const float *base, int64_t n, const float *queries, int64_t nq, int d, int k, int exclude_self,
+                    uint32_t *out_ids, float *out_dist, void *scratch, size_t scratch_bytes, hipStream_t st);
+}  // namespace nsg
+
+namespace nsg {
 
 // rows ids[b] of src[.][d] -> out[b][d] (one block per row)
 __global__ void ivf_gather_kernel(const float *src, int d, const uint32_t *ids, float *out) {
@@ -224,18 +232,30 @@ extern "C" int nsg_knn_ivf(const float *base, int64_t n, int32_t d, const uint32
     }
     // 3. cell by cell: probing points against members, merged into the lists.
     // Consecutive cells alternate between the caller's stream and a second
-    // one, each with its own row and result buffers, so that a cell's gathers
-    // and brute force overlap the previous cell's; the merges, which update
-    // the shared per-point lists, keep the cell order through events.
+    // one, each with its own row, result and brute-force scratch buffers
+    // (allocated once, for the largest cell), so that a cell's gathers and
+    // brute force overlap the previous cell's; the merges, which update the
+    // shared per-point lists, keep the cell order through events.
     const int kc = K + 1;
     float *bbuf[2] = {nullptr, nullptr}, *qbuf[2] = {nullptr, nullptr}, *cd[2] = {nullptr, nullptr};
     uint32_t *ci[2] = {nullptr, nullptr};
+    void *ws[2] = {nullptr, nullptr};
     for (int h = 0; h < 2; ++h)
         if ((rc = dalloc((void **)&bbuf[h], sizeof(float) * (size_t)mmax * d)) ||
             (rc = dalloc((void **)&qbuf[h], sizeof(float) * (size_t)qmax * d)) ||
             (rc = dalloc((void **)&ci[h], sizeof(uint32_t) * (size_t)qmax * kc)) ||
             (rc = dalloc((void **)&cd[h], sizeof(float) * (size_t)qmax * kc)))
             return rc;
+    size_t ws_bytes = 0;
+    for (int c = 0; c < nlist; ++c) {
+        const int64_t m = hc[c], q = hc[nlist + c];
+        if (m == 0 || q == 0) continue;
+        size_t b = 0;
+        if ((rc = bf_scratch_bytes(bbuf[0], m, qbuf[0], q, d, kc, &b))) return rc;
+        ws_bytes = std::max(ws_bytes, b);
+    }
+    for (int h = 0; h < 2; ++h)
+        if ((rc = dalloc(&ws[h], ws_bytes))) return rc;
     struct Side {
         hipStream_t s2 = nullptr;
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -266,7 +286,8 @@ extern "C" int nsg_knn_ivf(const float *base, int64_t n, int32_t d, const uint32
             hipLaunchKernelGGL(ivf_gather_kernel, dim3((unsigned)q), dim3(128), 0, s, base, d, qmember + qoff,
                                qbuf[h]);
             NSG_HIP(hipGetLastError());
-            if ((rc = nsg_knn_bruteforce(bbuf[h], m, qbuf[h], q, d, kc, 0, ci[h], cd[h], s))) return rc;
+            if ((rc = bf_with_scratch(bbuf[h], m, qbuf[h], q, d, kc, 0, ci[h], cd[h], ws[h], ws_bytes, s)))
+                return rc;
             // merges in cell order: after the previous cell's (other stream)
             if (done > 0) NSG_HIP(hipStreamWaitEvent(s, side.ev[h ^ 1], 0));
             hipLaunchKernelGGL(ivf_merge_kernel, dim3((unsigned)((q + wpb - 1) / wpb)), dim3(64 * wpb), lds, s,
