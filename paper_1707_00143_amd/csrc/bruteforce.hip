@@ -171,9 +171,10 @@ __device__ inline void wave_fence() {
 // B keeps every entry that can still be among the Kp best).  One wave: the
 // bucket of high words holding the Kp-th smallest is narrowed bit by bit from
 // the highest bit on which the keys differ (a radix select counting with
-// ballots); with slack it stops once the bucket and everything below it hold
-// at most Kp + slack entries.  Every load precedes every store (the stores
-// depend on ballots over all loaded keys).
+// ballots); it stops once the bucket and everything below it hold at most
+// Kp + slack entries (for slack = 0: once the bucket holds exactly the
+// entries still needed).  Every load precedes every store (the stores depend
+// on ballots over all loaded keys).
 __device__ __attribute__((noinline)) uint64_t wave_keep_smallest(uint64_t *buf, int c, int Kp, int slack, int lane,
                                                                  int *kept) {
     constexpr int M = 8;
@@ -218,7 +219,7 @@ __device__ __attribute__((noinline)) uint64_t wave_keep_smallest(uint64_t *buf, 
         } else {
             in_bucket = cnt;
         }
-        if (slack > 0 && in_bucket - need <= slack) {   // bucket [prefix, prefix + 2^b) and all below it
+        if (in_bucket - need <= slack) {   // bucket [prefix, prefix + 2^b) and all below it
             bound = (uint64_t)prefix + (1ull << b);
             break;
         }
