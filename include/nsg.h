@@ -317,7 +317,10 @@ int nsg_build(const float *base, int64_t n, int32_t d, const uint32_t *knn,
  * exact kNN graph.  out_ids [n][K], out_dist [n][K] (device).  Limits:
  * 1 <= nlist <= n, 1 <= nprobe <= min(nlist, 160), 1 <= K <= 159,
  * n * nprobe < 2^31.  Temporary device memory ≈ n (8 K + 24 nprobe + 24)
- * bytes plus the largest cell's rows.  Synchronous.
+ * bytes plus, twice (consecutive cells run on two streams), the largest
+ * cell's member and probing-point rows and the brute-force scratch of the
+ * largest cell (about 4.5 KiB per probing point, for at least 65,536
+ * points), all allocated before the first cell.  Synchronous.
  */
 int nsg_knn_ivf(const float *base, int64_t n, int32_t d, const uint32_t *pivots,
                 int32_t nlist, int32_t nprobe, int32_t K, uint32_t *out_ids,
