@@ -63,6 +63,33 @@ def test_bruteforce_knn_graph_excludes_self(nsg, n, d, k):
     assert r["ok"], {kk: v for kk, v in r.items() if kk != "bad"}
 
 
+@pytest.mark.parametrize("groups,copies,d,k,self_graph", [(1, 3_000, 64, 100, False), (1, 1_500, 200, 100, False),
+                                                          (30, 100, 96, 60, False), (25, 60, 300, 40, False),
+                                                          (40, 50, 96, 70, True), (20, 40, 160, 50, True)])
+def test_bruteforce_exact_ties(nsg, groups, copies, d, k, self_graph):
+    """Base rows repeated so that many rank values are exactly equal where
+    the candidate buffers are cut (every key equal when groups = 1): the ids
+    returned are distinct, the distances are the k smallest, and the id sets
+    differ from the oracle's only among rows at the k-th distance.  Both
+    stage-1 kernels (d <= 128 and d > 128), with and without the own row."""
+    dev = _dev()
+    rng = np.random.default_rng(groups * 1000 + d)
+    U = np.round(rng.normal(size=(groups, d)) * 8 + 50).astype(np.float32)
+    X = np.repeat(U, copies, axis=0)[rng.permutation(groups * copies)]
+    Q = X if self_graph else np.round(rng.normal(size=(17, d)) * 8 + 50).astype(np.float32)
+    Xd = torch.from_numpy(X).to(dev)
+    ids, dist = nsg.knn_bruteforce(Xd, Xd if self_graph else torch.from_numpy(Q).to(dev), k,
+                                   exclude_self=self_graph)
+    ids = ids.cpu().numpy().view(np.uint32)
+    assert (ids < len(X)).all()
+    assert all(len(set(r.tolist())) == k for r in ids)
+    if self_graph:
+        assert not (ids == np.arange(len(X))[:, None]).any()
+    o_ids, _ = oracle.knn(X, Q, k, exclude_self=bool(self_graph))
+    r = compare(X, Q, ids, dist.cpu().numpy(), o_ids, rtol=1e-5, min_match=1.0)
+    assert r["ok"], {kk: v for kk, v in r.items() if kk != "bad"}
+
+
 def test_bruteforce_knn_graph_tiny(nsg, tiny_index):
     dev = _dev()
     X = tiny_index["X"]
