@@ -714,10 +714,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) b
     }
 }
 
-// one wave per query: exact distances of all candidates, sort, first k
+// one wave per query: exact distances of all candidates, sort, first k.
+// vec4 (d % 4 == 0, 16-byte aligned rows): 8 candidates per round, 8 lanes
+// each reading 16 bytes at a time; else 4 candidates of 16 lanes, 4 bytes.
+// sort_n is a power of two of at least 32 (ncand >= Kp >= 32).
 __global__ void __launch_bounds__(256) bf_rerank_kernel(const float *base, const float *queries, int64_t nq,
                                                         int d, const uint32_t *cand, int ncand, int k,
-                                                        int sort_n, uint32_t *out_ids, float *out_dist) {
+                                                        int sort_n, int vec4, uint32_t *out_ids,
+                                                        float *out_dist) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t qi = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
@@ -725,20 +729,43 @@ __global__ void __launch_bounds__(256) bf_rerank_kernel(const float *base, const
     if (qi >= nq) return;
     const float *q = queries + qi * d;
     const uint32_t *c = cand + qi * (int64_t)ncand;
-    const int g = lane >> 4, li = lane & 15;
-    for (int r0 = 0; r0 < sort_n; r0 += 4) {
-        int r = r0 + g;
-        uint32_t id = r < ncand ? c[r] : NSG_SENT;
-        float acc = 0.0f;
-        if (id != NSG_SENT) {
-            const float *x = base + (int64_t)id * d;
-            for (int j = li; j < d; j += 16) {
-                float t = q[j] - x[j];
-                acc = fmaf(t, t, acc);
+    if (vec4) {
+        const int g = lane >> 3, li = lane & 7, d4 = d >> 2;
+        const float4 *q4 = reinterpret_cast<const float4 *>(q);
+        for (int r0 = 0; r0 < sort_n; r0 += 8) {
+            const int r = r0 + g;
+            const uint32_t id = r < ncand ? c[r] : NSG_SENT;
+            float acc = 0.0f;
+            if (id != NSG_SENT) {
+                const float4 *x4 = reinterpret_cast<const float4 *>(base + (int64_t)id * d);
+                for (int j = li; j < d4; j += 8) {
+                    const float4 u = q4[j], v = x4[j];
+                    const float t0 = u.x - v.x, t1 = u.y - v.y, t2 = u.z - v.z, t3 = u.w - v.w;
+                    acc = fmaf(t0, t0, acc);
+                    acc = fmaf(t1, t1, acc);
+                    acc = fmaf(t2, t2, acc);
+                    acc = fmaf(t3, t3, acc);
+                }
             }
+            for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            if (li == 0) a[r] = id == NSG_SENT ? ~0ull : bkey(acc, id);
         }
-        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (li == 0) a[r] = id == NSG_SENT ? ~0ull : bkey(acc, id);
+    } else {
+        const int g = lane >> 4, li = lane & 15;
+        for (int r0 = 0; r0 < sort_n; r0 += 4) {
+            const int r = r0 + g;
+            const uint32_t id = r < ncand ? c[r] : NSG_SENT;
+            float acc = 0.0f;
+            if (id != NSG_SENT) {
+                const float *x = base + (int64_t)id * d;
+                for (int j = li; j < d; j += 16) {
+                    const float t = q[j] - x[j];
+                    acc = fmaf(t, t, acc);
+                }
+            }
+            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            if (li == 0) a[r] = id == NSG_SENT ? ~0ull : bkey(acc, id);
+        }
     }
     wave_sort_buf(a, sort_n, sort_n, lane);
     for (int j = lane; j < k; j += 64) {
@@ -788,7 +815,7 @@ WideKernel wide_kernel_v(int d) {
 // candidate counts, and the offsets of its scratch in one block of memory.
 struct BFPlan {
     WideKernel wk;
-    int Kp, cap, nsplit, ncand, sort_n;
+    int Kp, cap, nsplit, ncand, sort_n, vec4;
     int64_t qtiles, split_len;
     size_t off_mu, off_xnorm, off_cand, off_cbuf, bytes;
 };
@@ -808,6 +835,7 @@ static int bf_plan(const float *base, int64_t n, const float *queries, int64_t n
                       (reinterpret_cast<uintptr_t>(queries) & 15) == 0;
     const int bq = wide ? 4 * kWideQW : CQ;
     P.qtiles = (nq + bq - 1) / bq;
+    P.vec4 = vec4 ? 1 : 0;
     if (wide) {
         P.wk = vec4 ? wide_kernel_v<true>(d) : wide_kernel_v<false>(d);
     } else {
@@ -879,8 +907,8 @@ static int bf_launch(const BFPlan &P, const float *base, int64_t n, const float 
     if (le == hipSuccess) {
         const int wpb = std::max(1, std::min(4, (int)(64 * 1024 / ((size_t)P.sort_n * 8))));
         hipLaunchKernelGGL(bf_rerank_kernel, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb),
-                           (size_t)P.sort_n * 8 * wpb, st, base, queries, nq, d, cand, P.ncand, k, P.sort_n, out_ids,
-                           out_dist);
+                           (size_t)P.sort_n * 8 * wpb, st, base, queries, nq, d, cand, P.ncand, k, P.sort_n, P.vec4,
+                           out_ids, out_dist);
     }
     const hipError_t e = le != hipSuccess ? le : hipGetLastError();
     if (e != hipSuccess) return fail(NSG_EDEVICE, "brute-force launch failed: %s", hipGetErrorString(e));
