@@ -90,6 +90,9 @@ def main():
                     choices=["sift1m_like", "deep_uneven", "gist_precision", "sift1m_shards", "sift1m_ablation"],
                     help="deep_uneven: DEEP-like unit vectors, 100k queries with uneven k and L served in "
                          "batches of 1000 by hipGraph replays of the persistent kernel (a secondary line)")
+    ap.add_argument("--inflight", type=int, default=16,
+                    help="deep_uneven: a count of batches in flight at once to measure besides 2, 4 and 8 (one "
+                         "captured graph and stream each)")
     ap.add_argument("--knn", default="exact", choices=["exact", "ivf"],
                     help="deep_uneven: the kNN graph by brute force, or the approximate inverted-file graph "
                          "(n / 10000 random pivot cells, 8 probed per point)")
@@ -1022,6 +1025,58 @@ def uneven(args, torch, nsg, datagen, dev):
     wall = time.time() - t0
     total_ms = float(np.sum(lat))
     ids = out_ids.cpu().numpy().view(np.uint32)
+
+    # the same stream with several batches in flight: batch j on stream
+    # j mod S, each stream with its own captured graph, input and output
+    # buffers (and work counter); one batch holds 1000 waves, so a single
+    # batch leaves most of the chip's wave slots idle
+    counts = sorted({2, 4, 8, max(1, args.inflight)})
+    streams = [torch.cuda.Stream() for _ in range(counts[-1])]
+    slots = []
+    for _ in range(counts[-1]):
+        q_, k_, L_ = torch.empty_like(qb), torch.empty_like(kb), torch.empty_like(Lb)
+        slots.append((q_, k_, L_, nsg.SearchGraph(ix, q_, k=k_, L=L_, L_scalar=500, out_stride=100, opts=opts)))
+    out_cc = torch.empty_like(out_ids)
+    # a query's result is its first k entries (the rest of the row is not written)
+    kmask = torch.arange(out_ids.shape[1], device=dev)[None, :] < kd[:, None]
+
+    def run_concurrent(S):
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        main = torch.cuda.current_stream()
+        start.record(main)
+        for st in streams[:S]:
+            st.wait_event(start)
+        lat_cc = []
+        for j, s0 in enumerate(range(0, nq, B)):
+            st = streams[j % S]
+            q_, k_, L_, g_ = slots[j % S]
+            with torch.cuda.stream(st):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(st)
+                q_.copy_(Qd[s0:s0 + B])
+                k_.copy_(kd[s0:s0 + B])
+                L_.copy_(Ld[s0:s0 + B])
+                o_ids, _ = g_.launch(st)
+                out_cc[s0:s0 + B].copy_(o_ids)
+                b.record(st)
+                lat_cc.append((a, b))
+        for st in streams[:S]:
+            main.wait_stream(st)
+        stop.record(main)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop), [a.elapsed_time(b) for a, b in lat_cc]
+
+    inflight = []
+    for S in counts:
+        out_cc.fill_(-1)
+        run_concurrent(S)
+        cc_ms, lat_cc = run_concurrent(S)
+        inflight.append({"batches_in_flight": S, "qps": round(nq / (cc_ms / 1e3), 1), "gpu_ms": round(cc_ms, 3),
+                         "p50_batch_ms": round(float(np.percentile(lat_cc, 50)), 4),
+                         "p99_batch_ms": round(float(np.percentile(lat_cc, 99)), 4),
+                         "ids_equal_one_in_flight": bool(torch.equal(out_cc[kmask], out_ids[kmask]))})
+        log(f"{S} batches in flight: {inflight[-1]}")
     tr = truth.cpu().numpy().view(np.uint32)
     rec = {}
     for kv in (1, 10, 100):
@@ -1037,7 +1092,7 @@ def uneven(args, torch, nsg, datagen, dev):
                    "p50_batch_ms": round(float(np.percentile(lat, 50)), 4),
                    "p99_batch_ms": round(float(np.percentile(lat, 99)), 4),
                    "wall_s": round(wall, 3), "recall_by_k": rec, "autotuned": best, "index_s": round(t_idx, 1),
-                   "knn_graph": knn_info},
+                   "knn_graph": knn_info, "concurrent": inflight},
     }
     print(json.dumps(res))
 
