@@ -6,11 +6,12 @@
 // v_mfma_f32_16x16x4f32, turned into rank values, and every value below the
 // query's current threshold is appended to that query's candidate buffer
 // (device memory: appends are rare once the threshold is tight).  A buffer
-// that could overflow on the next tile is cut back to its Kp best by a
-// radix select over the rank values (ballot counts, in registers), which
-// tightens the threshold (the buffer holds Kp + 2 tiles, so cuts are rare
-// once the threshold is tight).  Each block writes the ids of its Kp best per
-// query for its split.
+// that could overflow on the next tile is cut back to at most Kp + 32 keys
+// that include its Kp best, by a radix select over the rank values (ballot
+// counts, in registers) that stops as soon as a bound keeps that many; the
+// bound becomes the threshold (the buffer holds Kp + 2 tiles at least, so
+// cuts are rare once the threshold is tight).  Each block writes the ids of
+// its Kp best per query for its split (an exact cut).
 //  * d <= 128 (bf_wide_kernel): 4 waves x 32 queries per block; each wave
 //    keeps its centred queries as matrix-core operands in registers for the
 //    whole scan, owns all 64 rows of a tile and appends and compacts only its
