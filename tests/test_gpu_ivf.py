@@ -42,6 +42,22 @@ def test_ivf_graph_matches_oracle(nsg, n, nlist, nprobe, K):
     assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
 
 
+@pytest.mark.parametrize("n,d,nlist,nprobe,K", [(4_000, 200, 30, 2, 20), (3_000, 37, 25, 3, 16)])
+def test_ivf_graph_other_dims(nsg, n, d, nlist, nprobe, K):
+    """Cells searched by the other stage-1 kernel (d > 128, 32-dim chunks) and
+    by the 4-byte load paths (d not a multiple of 4)."""
+    dev = _dev()
+    rng = np.random.default_rng(n * d)
+    X = (rng.normal(size=(n, d)) * 4 + rng.integers(0, 6, size=(n, 1)) * 10).astype(np.float32)
+    piv = rng.choice(n, nlist, replace=False).astype(np.uint32)
+    ids, dist = nsg.knn_ivf(torch.from_numpy(X).to(dev), torch.from_numpy(piv.view(np.int32)).to(dev), nprobe, K)
+    ids, dist = ids.cpu().numpy().view(np.uint32), dist.cpu().numpy()
+    o_ids, _ = oracle.knn_ivf(X, piv, nprobe, K)
+    assert ((ids == SENT) == (o_ids == SENT)).mean() > 0.999
+    r = compare(X, X, ids, dist, o_ids)
+    assert r["ok"], {a: b for a, b in r.items() if a != "bad"}
+
+
 def test_all_cells_probed_is_the_exact_graph(nsg):
     dev = _dev()
     w = datagen.scaled(datagen.DEEP10M_LIKE, 8_000, 10)
