@@ -298,6 +298,48 @@ def test_persistent_batches_on_two_streams(tiny_gpu, nsg):
         assert torch.equal(ids, ref[0]) and torch.equal(dist, ref[1])
 
 
+def test_graphs_in_flight_on_four_streams(tiny_gpu, nsg):
+    """Four captured persistent batches (each with its own buffers and work
+    counter) replayed at once on four streams, batch j on stream j mod 4,
+    three rounds with fresh queries copied in on each stream: every query's
+    first k[i] entries equal its eager search."""
+    t = tiny_gpu
+    dev = t["Qd"].device
+    nq, S = 25, 4
+    k, L = datagen.uneven_kL(nq * 12, 11, k_choices=(1, 10), L_lo=10, L_hi=120)
+    kd_all = torch.from_numpy(k).to(dev)
+    Ld_all = torch.from_numpy(L).to(dev)
+    Qall = t["Qd"][torch.arange(nq * 12, device=dev) % t["Qd"].shape[0]].contiguous()
+    e_ids, e_dist = nsg.search_batched(t["ix"], Qall, k=kd_all, L=Ld_all, L_scalar=120, out_stride=10)
+    streams = [torch.cuda.Stream() for _ in range(S)]
+    slots = []
+    for _ in range(S):
+        q_ = torch.empty((nq, Qall.shape[1]), dtype=torch.float32, device=dev)
+        k_ = torch.empty(nq, dtype=torch.int32, device=dev)
+        L_ = torch.empty(nq, dtype=torch.int32, device=dev)
+        slots.append((q_, k_, L_, nsg.SearchGraph(t["ix"], q_, k=k_, L=L_, L_scalar=120, out_stride=10,
+                                                  opts=dict(persistent=1))))
+    out_ids = torch.full((nq * 12, 10), -1, dtype=torch.int32, device=dev)
+    out_dist = torch.full((nq * 12, 10), float("inf"), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    for j in range(12):
+        st = streams[j % S]
+        q_, k_, L_, g = slots[j % S]
+        with torch.cuda.stream(st):
+            rows = slice(j * nq, (j + 1) * nq)
+            q_.copy_(Qall[rows])
+            k_.copy_(kd_all[rows])
+            L_.copy_(Ld_all[rows])
+            ids, dist = g.launch(st)
+            out_ids[rows].copy_(ids)
+            out_dist[rows].copy_(dist)
+    torch.cuda.synchronize()
+    for i in range(nq * 12):
+        assert torch.equal(out_ids[i, :k[i]], e_ids[i, :k[i]]) and torch.equal(out_dist[i, :k[i]], e_dist[i, :k[i]])
+    for *_, g in slots:
+        g.close()
+
+
 @pytest.mark.parametrize("d,R", [(1024, 128), (1, 8), (37, 128), (129, 65)])
 def test_extreme_shapes_match_oracle(nsg, d, R):
     """The largest dimension and out-degree the library accepts (d = 1024,
