@@ -33,6 +33,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BX = 64;   // rows per base tile of the wide kernel
 constexpr int kCutSlack = 32;   // an intermediate cut keeps at most Kp + 32 keys
+// buffers hold at least Kp + 2 tiles and are cut once they could overflow on
+// the next tile, so a cut must leave at most Kp + one tile (64 rows or more)
+static_assert(kCutSlack <= BX, "a cut could leave too little room for the next tile");
 
 struct BFParams {
     const float *base, *queries;
