@@ -160,7 +160,20 @@ typedef struct nsg_search_opts {
                                 search of the NSG-Naive baseline, Sec. 4.1.2) or random starts
                                 (Sec. 4.1.3); ids >= n are ignored */
     int32_t init_n;          /* 0 .. 512; 0: start at the navigating node */
+    int32_t longest_first;   /* 1: start the batch's queries in order of decreasing squared distance
+                                to the start node (the first distance of every walk), so that the
+                                walks that tend to run longest start first and the batch does not
+                                end on a few late long walks; results are unchanged.  Applies to
+                                batches of 2 .. NSG_ORDER_MAX queries on one graph (larger batches,
+                                and partitioned or randomly started searches, run in the given
+                                order); 0: the given order */
+    uint32_t *order_scratch; /* device scratch of NSG_ORDER_MAX * 8 bytes for longest_first, or
+                                NULL: the calling stream's library buffer (allocated on first use,
+                                kept; calls on one stream share it in stream order) */
 } nsg_search_opts;
+
+/* largest batch that longest_first orders */
+#define NSG_ORDER_MAX 65536
 
 /*
  * Batched search with a per-query k[i] and L[i] (device int32 arrays, NULL =
@@ -251,7 +264,8 @@ void nsg_search_graph_destroy(nsg_search_graph *g);   /* NULL-safe; synchronises
 
 /*
  * Time candidate launch configurations of nsg_search_batched (lanes per row,
- * waves per block, visited-filter size, persistent grid) on the given batch
+ * waves per block, visited-filter size, persistent grid, longest_first for
+ * batches of at most NSG_ORDER_MAX queries) on the given batch
  * (scalar k, L) and return the fastest in *best (host; other fields zeroed)
  * with its mean time per call in *best_ms (host).  On input, best->learned_stop
  * is honoured (every candidate is timed with it; the other input fields are

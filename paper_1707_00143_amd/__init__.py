@@ -60,6 +60,8 @@ class SearchOpts(ctypes.Structure):
         ("clamped", ctypes.c_void_p),
         ("init_ids", ctypes.c_void_p),
         ("init_n", ctypes.c_int32),
+        ("longest_first", ctypes.c_int32),
+        ("order_scratch", ctypes.c_void_p),
     ]
 
 
@@ -461,7 +463,7 @@ def autotune(index, queries, k, L, trials=3, learned_stop=0, stream=None):
     _call("nsg_autotune", index.handle, _dev(queries, torch.float32, "queries"), queries.shape[0], int(k), int(L),
           int(trials), ctypes.byref(o), ctypes.byref(ms), _stream(stream))
     best = dict(lanes_per_row=o.lanes_per_row, hash_slots=o.hash_slots, waves_per_block=o.waves_per_block,
-                persistent=o.persistent)
+                persistent=o.persistent, longest_first=o.longest_first)
     return best, float(ms.value)
 
 

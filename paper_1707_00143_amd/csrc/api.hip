@@ -401,6 +401,7 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     if (o.blocks < 0) return fail(NSG_EINVAL, "blocks < 0");
     if (o.init_n < 0 || o.init_n > kMaxL) return fail(NSG_EINVAL, "init_n=%d out of range [0, %d]", o.init_n, kMaxL);
     if (o.init_n > 0 && !o.init_ids) return fail(NSG_EINVAL, "init_n > 0 needs init_ids");
+    if (o.longest_first != 0 && o.longest_first != 1) return fail(NSG_EINVAL, "longest_first must be 0 or 1");
     if (nq == 0) return NSG_OK;
     SearchArgs a{};
     a.idx = idx;
@@ -429,6 +430,8 @@ extern "C" int nsg_search_batched(const nsg_index *idx, const float *queries, in
     a.nedges = o.nedges;
     a.lanes_per_row = o.lanes_per_row;
     a.counter = o.counter;
+    a.longest_first = o.longest_first;
+    a.order_scratch = o.order_scratch;
     a.clamped = o.clamped;
     a.init_ids = o.init_ids;
     a.init_n = o.init_n;
@@ -563,6 +566,7 @@ struct nsg_search_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     unsigned int *counter = nullptr;
+    uint32_t *order = nullptr;             // scratch of the longest-first order
     const nsg_index *stop_idx = nullptr;   // index whose early-stop model the graph holds
 };
 
@@ -572,6 +576,7 @@ extern "C" void nsg_search_graph_destroy(nsg_search_graph *g) {
     if (g->exec) hipGraphExecDestroy(g->exec);
     if (g->graph) hipGraphDestroy(g->graph);
     hipFree(g->counter);
+    hipFree(g->order);
     if (g->stop_idx) g->stop_idx->stop_graphs.fetch_sub(1);
     delete g;
 }
@@ -593,6 +598,13 @@ extern "C" int nsg_search_graph_create(const nsg_index *idx, const float *querie
             return fail(NSG_ENOMEM, "counter allocation failed");
         }
         o.counter = g->counter;
+    }
+    if (o.longest_first && !o.order_scratch) {
+        if (hipMalloc(&g->order, sizeof(uint32_t) * 2 * NSG_ORDER_MAX) != hipSuccess) {
+            nsg_search_graph_destroy(g);
+            return fail(NSG_ENOMEM, "order scratch allocation failed");
+        }
+        o.order_scratch = g->order;
     }
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
@@ -672,12 +684,15 @@ extern "C" int nsg_autotune(const nsg_index *idx, const float *queries, int64_t 
             continue;   // too few lanes for the row, or half of them idle
         for (int hi = 0; hi < 3 && rc == NSG_OK; ++hi) {
             for (int wi = 0; wi < 3 && rc == NSG_OK; ++wi)
-                for (int pers = 0; pers < 2 && rc == NSG_OK; ++pers) {
+                for (int tr = 0; tr < 4 && rc == NSG_OK; ++tr) {
+                    const int pers = tr & 1, lf = tr >> 1;
+                    if (lf && nq > NSG_ORDER_MAX) continue;
                     nsg_search_opts o{};
                     o.lanes_per_row = lprs[li];
                     o.hash_slots = hashes[hi];
                     o.waves_per_block = wpbs[wi];
                     o.persistent = pers;
+                    o.longest_first = lf;
                     o.learned_stop = learned;
                     o.counter = ctr;
                     int r = nsg_search_batched(idx, queries, nq, nullptr, nullptr, k, L, k, ids, dist, &o, stream);

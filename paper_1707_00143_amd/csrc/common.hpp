@@ -103,6 +103,8 @@ struct SearchArgs {
     int32_t feature_hop;      // decision / trace hop (0: 16)
     int32_t lanes_per_row;    // 0: default layout
     unsigned int *counter;    // persistent work counter (NULL: the calling stream's library counter)
+    int longest_first;        // start the queries in order of decreasing distance to the start node
+    uint32_t *order_scratch;  // NSG_ORDER_MAX * 8 bytes for that order (NULL: the stream's library buffer)
     int32_t *clamped;         // queries whose k[i] / L[i] were clamped (device counter), or NULL
     int32_t *budget;
     int32_t max_hops;

@@ -48,6 +48,109 @@ static int stream_counter(hipStream_t st, unsigned int **out) {
     return NSG_OK;
 }
 
+// Longest walks first.  A batch larger than the chip's wave slots ends on
+// the walks that started last; starting the queries farthest from the start
+// node first (their squared distance to it, the first distance of every
+// walk, tracks how long the walk runs) leaves shorter walks for the end.
+// The order only needs to be approximate: one block sorts the queries into
+// 1024 buckets of distance between the batch's extremes (farthest first;
+// NaN last), in any order within a bucket.
+__global__ void order_key_kernel(const float *queries, int64_t nq, int d, const float *srow, float *dist) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i >= nq) return;
+    const float *q = queries + i * d;
+    float s = 0.0f;
+    for (int j = lane; j < d; j += 64) {
+        const float t = q[j] - srow[j];
+        s = fmaf(t, t, s);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) dist[i] = s;
+}
+
+constexpr int kOrderBuckets = 1024;   // one per thread of the ordering block
+
+__device__ inline int order_bucket(float x, float hi, float scale) {
+    if (!(x == x)) return kOrderBuckets - 1;
+    const float f = (hi - x) * scale;   // NaN when x and hi are both infinite
+    if (!(f > 0.0f)) return 0;
+    return f >= (float)(kOrderBuckets - 1) ? kOrderBuckets - 1 : (int)f;
+}
+
+__global__ void __launch_bounds__(kOrderBuckets) order_bucket_kernel(const float *dist, int nq, uint32_t *order) {
+    __shared__ uint32_t cnt[kOrderBuckets];
+    __shared__ float wlo[kOrderBuckets / 64], whi[kOrderBuckets / 64];
+    __shared__ uint32_t wsum[kOrderBuckets / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // extremes of the batch's distances
+    float lo = INFINITY, hi = -INFINITY;
+    for (int i = t; i < nq; i += kOrderBuckets) {
+        const float x = dist[i];
+        if (x == x) {
+            lo = fminf(lo, x);
+            hi = fmaxf(hi, x);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o));
+        hi = fmaxf(hi, __shfl_xor(hi, o));
+    }
+    if (lane == 0) {
+        wlo[w] = lo;
+        whi[w] = hi;
+    }
+    cnt[t] = 0u;
+    __syncthreads();
+    lo = wlo[0];
+    hi = whi[0];
+    for (int v = 1; v < kOrderBuckets / 64; ++v) {
+        lo = fminf(lo, wlo[v]);
+        hi = fmaxf(hi, whi[v]);
+    }
+    const float scale = hi > lo ? (float)kOrderBuckets / (hi - lo) : 0.0f;
+    // bucket sizes
+    for (int i = t; i < nq; i += kOrderBuckets) atomicAdd(&cnt[order_bucket(dist[i], hi, scale)], 1u);
+    __syncthreads();
+    // exclusive scan of the sizes: within each wave, then over the waves
+    const uint32_t c = cnt[t];
+    uint32_t incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int v = 0; v < w; ++v) base += wsum[v];
+    __syncthreads();
+    cnt[t] = base + incl - c;   // first position of bucket t
+    __syncthreads();
+    for (int i = t; i < nq; i += kOrderBuckets) order[atomicAdd(&cnt[order_bucket(dist[i], hi, scale)], 1u)] = (uint32_t)i;
+}
+
+// Scratch of the order for calls that bring none: one per (device, stream),
+// like the work counter.
+static int stream_order_scratch(hipStream_t st, uint32_t **out) {
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, uint32_t *> bufs;
+    int dev = 0;
+    NSG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(dev, st);
+    auto it = bufs.find(key);
+    if (it != bufs.end()) {
+        *out = it->second;
+        return NSG_OK;
+    }
+    uint32_t *b = nullptr;
+    if (hipMalloc((void **)&b, sizeof(uint32_t) * 2 * NSG_ORDER_MAX) != hipSuccess)
+        return fail(NSG_ENOMEM, "order scratch allocation failed");
+    bufs[key] = b;
+    *out = b;
+    return NSG_OK;
+}
+
 kfn_t pick_search_kernel_f32(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_f32_stop(int lpr, int cpl, int nch);
 kfn_t pick_search_kernel_f32_full(int lpr, int cpl, int nch);
@@ -206,6 +309,21 @@ int launch_search(const SearchArgs &a) {
     } else {
         blocks = (a.nq + wpb - 1) / wpb;
         p.counter = nullptr;
+    }
+    p.order = nullptr;
+    if (a.longest_first && a.nq >= 2 && a.nq <= NSG_ORDER_MAX && p.shards == 1 && p.init_n == 0) {
+        uint32_t *scr = a.order_scratch;
+        if (!scr) {
+            int rc = stream_order_scratch(a.stream, &scr);
+            if (rc) return rc;
+        }
+        const float *srow = ix->base_f32 + (int64_t)p.start * (ix->row_chunks_f32 * 4);
+        float *dist = reinterpret_cast<float *>(scr);
+        hipLaunchKernelGGL(order_key_kernel, dim3((unsigned)((a.nq + 3) / 4)), dim3(256), 0, a.stream, a.queries,
+                           a.nq, ix->d, srow, dist);
+        hipLaunchKernelGGL(order_bucket_kernel, dim3(1), dim3(kOrderBuckets), 0, a.stream, dist, (int)a.nq,
+                           scr + NSG_ORDER_MAX);
+        p.order = scr + NSG_ORDER_MAX;
     }
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, p);
     hipError_t e = hipGetLastError();

@@ -25,6 +25,7 @@ struct KParams {
     float rr_eta;                // the index's bound E (< 0: re-rank the whole pool)
     float rr_rho;                // relative rounding bound of a computed squared distance, (d + 4) 2^-24
     unsigned int *counter;
+    const uint32_t *order;       // work slot -> query index (longest walks first), or NULL: identity
     int32_t *clamped;            // queries whose k / L were clamped into range, or NULL
     int64_t *hops, *ndist, *nedges;
     int max_hops;                // expansion budget for every query (0: none)
@@ -329,15 +330,18 @@ search_kernel(KParams p) {
     float *cdist = reinterpret_cast<float *>(cid + kMaxR);   // and distances
     const int H = 1 << p.hash_bits;
 
-    int64_t qi;
+    // work slots in launch order (the counter, or the wave's place in the
+    // grid), mapped to queries through the order when one is given
+    int64_t slot;
     if (p.counter) {
         unsigned int t = 0;
         if (lane == 0) t = atomicAdd(p.counter, 1u);
-        qi = __builtin_amdgcn_readfirstlane((int)t);
+        slot = __builtin_amdgcn_readfirstlane((int)t);
     } else {
-        qi = (int64_t)blockIdx.x * wpb + wave;
+        slot = (int64_t)blockIdx.x * wpb + wave;
     }
-    while (qi < p.nq) {
+    while (slot < p.nq) {
+        const int64_t qi = p.order ? (int64_t)__builtin_amdgcn_readfirstlane((int)p.order[slot]) : slot;
         const int64_t qrow = p.shards > 1 ? qi / p.shards : qi;
         const float *q = p.queries + qrow * (int64_t)p.d;
         int kq = p.k_arr ? p.k_arr[qi] : p.k_scalar;
@@ -554,7 +558,7 @@ search_kernel(KParams p) {
         if (!p.counter) break;
         unsigned int t = 0;
         if (lane == 0) t = atomicAdd(p.counter, 1u);
-        qi = __builtin_amdgcn_readfirstlane((int)t);
+        slot = __builtin_amdgcn_readfirstlane((int)t);
     }
 }
 

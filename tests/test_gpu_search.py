@@ -298,6 +298,51 @@ def test_persistent_batches_on_two_streams(tiny_gpu, nsg):
         assert torch.equal(ids, ref[0]) and torch.equal(dist, ref[1])
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_longest_first_changes_no_result(tiny_gpu, nsg, storage):
+    """Starting the queries farthest from the navigating node first (the
+    longest_first option) changes the schedule only: every query's ids,
+    distances and expansion count equal those of the given order, for both
+    grids, uneven k / L, a captured graph, and a batch above the sorted
+    limit (which runs in the given order)."""
+    t = tiny_gpu
+    dev = t["Qd"].device
+    ix = nsg.load_index(t["Xd"], torch.from_numpy(t["graph"].view(np.int32)).to(dev), t["nav"], storage)
+    nq = 300
+    Q = t["Qd"][torch.arange(nq, device=dev) % t["Qd"].shape[0]].contiguous()
+    k, L = datagen.uneven_kL(nq, 5, k_choices=(1, 10), L_lo=10, L_hi=120)
+    kd, Ld = torch.from_numpy(k).to(dev), torch.from_numpy(L).to(dev)
+    for persistent in (0, 1):
+        for wpb in (1, 2):
+            res = []
+            for lf in (0, 1):
+                hops = torch.zeros(nq, dtype=torch.int64, device=dev)
+                ids, dist = nsg.search_batched(ix, Q, k=kd, L=Ld, L_scalar=120, out_stride=10,
+                                               opts=dict(persistent=persistent, waves_per_block=wpb,
+                                                         longest_first=lf, hops=hops))
+                res.append((ids, dist, hops))
+            torch.cuda.synchronize()
+            for i in range(nq):
+                assert torch.equal(res[0][0][i, :k[i]], res[1][0][i, :k[i]])
+                assert torch.equal(res[0][1][i, :k[i]], res[1][1][i, :k[i]])
+            assert torch.equal(res[0][2], res[1][2])
+    g = nsg.SearchGraph(ix, Q, k=kd, L=Ld, L_scalar=120, out_stride=10, opts=dict(persistent=1, longest_first=1))
+    e_ids, e_dist = nsg.search_batched(ix, Q, k=kd, L=Ld, L_scalar=120, out_stride=10)
+    for _ in range(3):
+        ids, dist = g.launch()
+        torch.cuda.synchronize()
+        for i in range(0, nq, 7):
+            assert torch.equal(ids[i, :k[i]], e_ids[i, :k[i]]) and torch.equal(dist[i, :k[i]], e_dist[i, :k[i]])
+    g.close()
+    big = t["Qd"][torch.arange(65_537, device=dev) % t["Qd"].shape[0]].contiguous()
+    a = nsg.search_batched(ix, big, k_scalar=10, L_scalar=40, opts=dict(longest_first=1))
+    b = nsg.search_batched(ix, big, k_scalar=10, L_scalar=40)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    with pytest.raises(nsg.NSGError):
+        nsg.search_batched(ix, Q, k_scalar=10, L_scalar=40, opts=dict(longest_first=2))
+    ix.close()
+
+
 def test_graphs_in_flight_on_four_streams(tiny_gpu, nsg):
     """Four captured persistent batches (each with its own buffers and work
     counter) replayed at once on four streams, batch j on stream j mod 4,
