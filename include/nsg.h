@@ -106,6 +106,9 @@ int nsg_index_info(const nsg_index *idx, int64_t *n, int32_t *d, int32_t *R,
  * nq = 0 is a no-op.  Batches of 4096 queries or more run on a persistent
  * grid whose work counter the library allocates once per stream (the first
  * such call on a stream allocates it; later calls on that stream reuse it).
+ * Batches of 8192 .. NSG_ORDER_MAX queries start the queries farthest from
+ * the navigating node first (nsg_search_opts.longest_first; same results),
+ * with an order buffer held per stream in the same way.
  */
 int nsg_search(const nsg_index *idx, const float *queries, int64_t nq,
                int32_t k, int32_t L, uint32_t *out_ids, float *out_dist,

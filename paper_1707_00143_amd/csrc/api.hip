@@ -176,6 +176,8 @@ static int grid_for(int64_t cnt) {
 }
 
 const int64_t kPersistentMinBatch = 4096;
+// batches that fill the chip's wave slots more than once: longest walks first
+const int64_t kLongestFirstMinBatch = 8192;
 
 // a query visits roughly 25 nodes per pool entry; size the filter to that
 // (it forgets beyond, which only costs recomputation)
@@ -357,6 +359,7 @@ extern "C" int nsg_search(const nsg_index *idx, const float *queries, int64_t nq
     a.rerank = idx->storage != NSG_F32;
     // large batches: persistent grid (work stealing evens out per-query cost)
     a.persistent = nq >= kPersistentMinBatch;
+    a.longest_first = nq >= kLongestFirstMinBatch;
     a.start_override = NSG_SENT;
     a.self_offset = -1;
     a.stream = (hipStream_t)stream;
