@@ -182,7 +182,8 @@ def test_learned_stop_every_format_and_pool_size(nsg, tiny_index, dt, L, hop):
     expansions): with the budgets the kernel reports, the walk equals the
     oracle's Algorithm 1 over the decoded rows stopped after that many
     expansions, and the output equals the oracle's FP32 re-rank of that
-    pool (FP32: the walk's own output)."""
+    pool (FP32: the walk's own output); started longest first, every output
+    and budget is the same."""
     dev = _dev()
     from paper_1707_00143_amd import learned_stop as ls
     X, G, nav, Q = tiny_index["X"], tiny_index["graph"], tiny_index["nav"], tiny_index["Q"]
@@ -195,6 +196,9 @@ def test_learned_stop_every_format_and_pool_size(nsg, tiny_index, dt, L, hop):
     Bw = torch.zeros(nq, dtype=torch.int32, device=dev)
     ids, dist = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(learned_stop=1, budget=Bu))
     wi, wd = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(learned_stop=1, budget=Bw, rerank=-1))
+    Bl = torch.zeros(nq, dtype=torch.int32, device=dev)
+    li, ld = nsg.search_batched(ix, Qd, k_scalar=k, L_scalar=L, opts=dict(learned_stop=1, budget=Bl, longest_first=1))
+    assert torch.equal(li, ids) and torch.equal(ld, dist) and torch.equal(Bl, Bu)   # the start order changes nothing
     Bu = _np(Bu)
     assert (Bu == _np(Bw)).all() and set(Bu.tolist()) <= set(ls.GRID) and Bu.min() >= hop
     Xt = X if dt == "f32" else oracle.quantize(dt, X, oracle.scales(dt, X))[1]
